@@ -1,0 +1,151 @@
+/*
+ * ssgpu.h -- C ABI of the MI355X (gfx950) Super Smoother period search.
+ *
+ * Method: Gowanlock, Butler, Trilling & McNeill, "GPU-Enabled Searches for
+ * Periodic Signals of Unknown Shape" (arXiv 2111.07396).  For every
+ * (object, trial frequency) pair the library folds the light curve at the
+ * trial period, sorts it by phase, runs Friedman's variable-span Super
+ * Smoother (Listing 1, Sec. 2.2) or the single-pass generalized-validation
+ * variant (Sec. 3), scores the fit and reduces the scores to a periodogram
+ * and a best period (Alg. 1).
+ *
+ * Conventions shared by every entry point
+ *  - Every data pointer is a DEVICE pointer on the context's device, owned by
+ *    the caller.  The library never frees or retains caller memory.
+ *  - Calls are asynchronous on the HIP stream passed as `stream`
+ *    (hipStream_t, NULL = the default stream).  Outputs are valid once that
+ *    stream has been synchronized.  Planning reads the catalog offsets back
+ *    to the host (8 bytes per object) with a synchronous copy on `stream`.
+ *  - Return value: SS_OK (0) or a negative SS_ERR_* code.  Argument errors
+ *    are detected before any work is enqueued; ss_last_error() returns a
+ *    thread-local message for the last failing call.
+ *  - Data problems of one object never fail a call: they are reported in
+ *    obj_status[] (SS_OBJ_*), that object's periodogram row is NaN, its
+ *    best index is -1 and its best period/power are NaN.
+ *  - A context is not thread-safe; use one context per host thread.
+ */
+#ifndef SSGPU_H
+#define SSGPU_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes */
+#define SS_OK 0
+#define SS_ERR_INVALID_ARG (-1) /* null pointer, bad size, bad grid/span/precision */
+#define SS_ERR_HIP (-2)         /* a HIP runtime call failed (message has the hipError text) */
+#define SS_ERR_OOM (-3)         /* workspace allocation failed */
+#define SS_ERR_UNSUPPORTED (-4) /* e.g. an object longer than SS_MAX_POINTS */
+
+/* ---- per-object status (obj_status[]) */
+#define SS_OBJ_OK 0
+#define SS_OBJ_TOO_FEW 1    /* fewer than 5 points */
+#define SS_OBJ_BAD_ERR 2    /* an error bar e <= 0 or non-finite */
+#define SS_OBJ_NONFINITE 3  /* a non-finite t or y */
+#define SS_OBJ_CONST_MAG 4  /* chi0 == 0: constant magnitudes */
+/* Precedence when several apply: TOO_FEW, NONFINITE, BAD_ERR, CONST_MAG. */
+
+/* ---- precision (ss_params.precision) */
+#define SS_FP64 0  /* every sum and fit in FP64; periodogram is double */
+#define SS_FP32C 1 /* FP32 arithmetic with compensated (two-float) window sums;
+                      FP64 fold and chi^2/chi0 normalisation; periodogram is float */
+
+/* ---- method (ss_best_period) */
+#define SS_METHOD_SS 0   /* Listing 1: cross-validated variable-span smoother */
+#define SS_METHOD_SSSP 1 /* Sec. 3: single-pass generalized validation */
+
+/* Largest light curve the library accepts (points per object). */
+#define SS_MAX_POINTS 4096
+
+typedef struct ss_ctx ss_ctx;
+
+/* Trial frequencies f_k = f_min + k*df, df = (f_max - f_min)/n_freq,
+ * k = 0 .. n_freq-1: the even grid on [f_min, f_max) of App. A / Alg. 1.
+ * Requires 0 < f_min < f_max and n_freq >= 1. */
+typedef struct {
+    double f_min;
+    double f_max;
+    int64_t n_freq;
+} ss_grid;
+
+/* Smoother parameters.  span_min/mid/max are the tweeter, midrange and woofer
+ * spans of Listing 1 (defaults 0.05, 0.2, 0.5; need 0 < min < mid < max <= 1).
+ * alpha is the bass-enhancement exponent (Listing 1: applied when
+ * 0 < alpha <= 10; default 9, the paper's choice for catalogs, Sec. 5.1).
+ * fixed_span > 0 replaces the variable span by one smooth at that span
+ * (Listing 1's fixed-span branch; for the single-pass variant it leaves one
+ * candidate span).  flags: reserved, must be 0. */
+typedef struct {
+    double span_min;
+    double span_mid;
+    double span_max;
+    double alpha;
+    double fixed_span;
+    int32_t precision;
+    int32_t flags;
+} ss_params;
+
+/* A catalog of light curves in CSR form (device memory, FP64):
+ * object o owns points offsets[o] .. offsets[o+1]-1 of t (days), y
+ * (magnitudes) and e (error bars).  offsets[0] == 0, non-decreasing, n_obj+1
+ * entries.  Points need not be time-sorted. */
+typedef struct {
+    int64_t n_obj;
+    const int64_t *offsets;
+    const double *t;
+    const double *y;
+    const double *e;
+} ss_catalog;
+
+/* Fills *p with the defaults above (FP64). */
+void ss_params_default(ss_params *p);
+
+/* Creates a context bound to HIP device `device`.  The context owns a
+ * workspace that grows on demand and is freed by ss_ctx_destroy. */
+int ss_ctx_create(int device, ss_ctx **out);
+void ss_ctx_destroy(ss_ctx *ctx);
+
+/* Periodogram of the Super Smoother (Alg. 1 with Listing 1):
+ * pgram[o*n_freq + k] = 1 - chi2(o, f_k)/chi0(o), where chi2 is the weighted
+ * residual sum of the smoothed phase curve and chi0 the weighted sum of
+ * squares about the weighted mean.  pgram is double (SS_FP64) or float
+ * (SS_FP32C), n_obj*n_freq entries; obj_status has n_obj entries. */
+int ss_periodogram(ss_ctx *ctx, const ss_catalog *cat, const ss_grid *grid,
+                   const ss_params *params, void *pgram, int32_t *obj_status, void *stream);
+
+/* Same for the single-pass generalized-validation variant (Sec. 3): per trial
+ * the candidate span with the smallest GCV = RSS/(1 - TR/n)^2 is kept and
+ * chi2 = its RSS.  params.alpha is ignored. */
+int sssp_periodogram(ss_ctx *ctx, const ss_catalog *cat, const ss_grid *grid,
+                     const ss_params *params, void *pgram, int32_t *obj_status, void *stream);
+
+/* Best period per object without materialising the periodogram (Alg. 1
+ * findPeriod): best_idx[o] = the lowest k attaining the largest P (NaN
+ * skipped), best_period[o] = 1/f_k, best_power[o] = that P (as double).
+ * method = SS_METHOD_SS or SS_METHOD_SSSP.  Each output has n_obj entries. */
+int ss_best_period(ss_ctx *ctx, int32_t method, const ss_catalog *cat, const ss_grid *grid,
+                   const ss_params *params, int64_t *best_idx, double *best_period,
+                   double *best_power, int32_t *obj_status, void *stream);
+
+/* Kernel timing, for benchmarks.  With timing enabled, every call records HIP
+ * events on its stream around each launch of the fused trial kernel (all size
+ * classes).  ss_ctx_trial_kernel_ms waits for the last call's events and
+ * returns the summed duration of its trial-kernel launches in milliseconds
+ * and their count.  Returns SS_ERR_INVALID_ARG if timing was off. */
+int ss_ctx_set_timing(ss_ctx *ctx, int enable);
+int ss_ctx_trial_kernel_ms(ss_ctx *ctx, double *ms, int32_t *n_launches);
+
+/* Message for the last failing call on this host thread ("" if none). */
+const char *ss_last_error(void);
+
+/* ABI version (major*100 + minor). */
+int ss_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SSGPU_H */

@@ -1,0 +1,224 @@
+"""Python binding of the gfx950 Super Smoother period search (``libssgpu.so``).
+
+Argument marshalling only: every step of the search runs in the HIP library
+behind the C ABI of ``include/ssgpu.h``.  PyTorch supplies device memory and
+the stream; tensors are passed as raw device pointers.  Importing this module
+does not touch the GPU; the first call loads the library and fails loudly if
+it has not been built (``python -m paper_2111_07396_amd.build``).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libssgpu.so")
+
+SS_OK = 0
+SS_ERR_INVALID_ARG, SS_ERR_HIP, SS_ERR_OOM, SS_ERR_UNSUPPORTED = -1, -2, -3, -4
+SS_FP64, SS_FP32C = 0, 1
+SS_METHOD_SS, SS_METHOD_SSSP = 0, 1
+OBJ_OK, OBJ_TOO_FEW, OBJ_BAD_ERR, OBJ_NONFINITE, OBJ_CONST_MAG = 0, 1, 2, 3, 4
+MAX_POINTS = 4096
+
+EXPORTED = ("ss_params_default", "ss_ctx_create", "ss_ctx_destroy", "ss_periodogram",
+            "sssp_periodogram", "ss_best_period", "ss_ctx_set_timing", "ss_ctx_trial_kernel_ms",
+            "ss_last_error", "ss_version")
+
+
+class SSError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"ssgpu error {code}: {msg}")
+        self.code = code
+
+
+class _Grid(ctypes.Structure):
+    _fields_ = [("f_min", ctypes.c_double), ("f_max", ctypes.c_double),
+                ("n_freq", ctypes.c_int64)]
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("span_min", ctypes.c_double), ("span_mid", ctypes.c_double),
+                ("span_max", ctypes.c_double), ("alpha", ctypes.c_double),
+                ("fixed_span", ctypes.c_double), ("precision", ctypes.c_int32),
+                ("flags", ctypes.c_int32)]
+
+
+class _Catalog(ctypes.Structure):
+    _fields_ = [("n_obj", ctypes.c_int64), ("offsets", ctypes.c_void_p),
+                ("t", ctypes.c_void_p), ("y", ctypes.c_void_p), ("e", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Loads libssgpu.so (raises if it is missing: there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built; run `python -m paper_2111_07396_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+    lib.ss_params_default.argtypes = [ctypes.POINTER(_Params)]
+    lib.ss_params_default.restype = None
+    lib.ss_ctx_create.argtypes = [ctypes.c_int, ctypes.POINTER(vp)]
+    lib.ss_ctx_create.restype = ctypes.c_int
+    lib.ss_ctx_destroy.argtypes = [vp]
+    lib.ss_ctx_destroy.restype = None
+    for name in ("ss_periodogram", "sssp_periodogram"):
+        f = getattr(lib, name)
+        f.argtypes = [vp, ctypes.POINTER(_Catalog), ctypes.POINTER(_Grid), ctypes.POINTER(_Params),
+                      vp, vp, vp]
+        f.restype = ctypes.c_int
+    lib.ss_best_period.argtypes = [vp, i32, ctypes.POINTER(_Catalog), ctypes.POINTER(_Grid),
+                                   ctypes.POINTER(_Params), vp, vp, vp, vp, vp]
+    lib.ss_best_period.restype = ctypes.c_int
+    lib.ss_ctx_set_timing.argtypes = [vp, ctypes.c_int]
+    lib.ss_ctx_set_timing.restype = ctypes.c_int
+    lib.ss_ctx_trial_kernel_ms.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
+                                           ctypes.POINTER(ctypes.c_int32)]
+    lib.ss_ctx_trial_kernel_ms.restype = ctypes.c_int
+    lib.ss_last_error.argtypes = []
+    lib.ss_last_error.restype = ctypes.c_char_p
+    lib.ss_version.argtypes = []
+    lib.ss_version.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != SS_OK:
+        raise SSError(rc, _lib.ss_last_error().decode())
+
+
+@dataclass
+class Params:
+    span_min: float = 0.05
+    span_mid: float = 0.2
+    span_max: float = 0.5
+    alpha: float = 9.0
+    fixed_span: float = 0.0
+    precision: int = SS_FP64
+    flags: int = 0
+
+    def _c(self) -> _Params:
+        return _Params(self.span_min, self.span_mid, self.span_max, self.alpha, self.fixed_span,
+                       self.precision, self.flags)
+
+
+@dataclass
+class DeviceCatalog:
+    """A catalog resident in device memory (CSR, float64)."""
+    offsets: torch.Tensor  # int64 [n_obj + 1]
+    t: torch.Tensor
+    y: torch.Tensor
+    e: torch.Tensor
+
+    @property
+    def n_obj(self) -> int:
+        return int(self.offsets.numel() - 1)
+
+    @staticmethod
+    def from_numpy(offsets, t, y, e, device="cuda") -> "DeviceCatalog":
+        def tt(a, dt):
+            return torch.as_tensor(a, dtype=dt).to(device).contiguous()
+        return DeviceCatalog(tt(offsets, torch.int64), tt(t, torch.float64),
+                             tt(y, torch.float64), tt(e, torch.float64))
+
+    def _c(self) -> _Catalog:
+        for a, dt in ((self.offsets, torch.int64), (self.t, torch.float64),
+                      (self.y, torch.float64), (self.e, torch.float64)):
+            if a.dtype != dt or not a.is_cuda or not a.is_contiguous():
+                raise ValueError("catalog tensors must be contiguous CUDA tensors "
+                                 "(offsets int64; t, y, e float64)")
+        return _Catalog(self.n_obj, self.offsets.data_ptr(), self.t.data_ptr(),
+                        self.y.data_ptr(), self.e.data_ptr())
+
+
+def _stream_ptr(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Context:
+    """Owns an ss_ctx (workspace) on one device."""
+
+    def __init__(self, device: int = 0):
+        lib = load_library()
+        self._h = ctypes.c_void_p()
+        _check(lib.ss_ctx_create(device, ctypes.byref(self._h)))
+        self.device = device
+
+    def close(self):
+        if self._h:
+            _lib.ss_ctx_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_timing(self, enable: bool = True):
+        """Record HIP events around the fused trial-kernel launches of each call."""
+        _check(_lib.ss_ctx_set_timing(self._h, int(bool(enable))))
+
+    def trial_kernel_ms(self):
+        """(milliseconds, launches) of the trial kernels of the last call."""
+        ms = ctypes.c_double(0.0)
+        n = ctypes.c_int32(0)
+        _check(_lib.ss_ctx_trial_kernel_ms(self._h, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
+    def _pgram(self, fn, cat: DeviceCatalog, grid, params: Params, out=None, status=None,
+               stream=None):
+        n_obj = cat.n_obj
+        dt = torch.float64 if params.precision == SS_FP64 else torch.float32
+        dev = cat.offsets.device
+        if out is None:
+            out = torch.empty((n_obj, int(grid[2])), dtype=dt, device=dev)
+        if status is None:
+            status = torch.empty(n_obj, dtype=torch.int32, device=dev)
+        g = _Grid(float(grid[0]), float(grid[1]), int(grid[2]))
+        c = cat._c()
+        p = params._c()
+        _check(fn(self._h, ctypes.byref(c), ctypes.byref(g), ctypes.byref(p),
+                  ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(status.data_ptr()),
+                  _stream_ptr(stream)))
+        return out, status
+
+    def ss_periodogram(self, cat, grid, params=None, out=None, status=None, stream=None):
+        """P[o, k] of the Super Smoother (Listing 1) on grid (fmin, fmax, n_freq)."""
+        return self._pgram(_lib.ss_periodogram, cat, grid, params or Params(), out, status,
+                           stream)
+
+    def sssp_periodogram(self, cat, grid, params=None, out=None, status=None, stream=None):
+        """P[o, k] of the single-pass generalized-validation variant (Sec. 3)."""
+        return self._pgram(_lib.sssp_periodogram, cat, grid, params or Params(), out, status,
+                           stream)
+
+    def ss_best_period(self, method, cat, grid, params=None, out=None, stream=None):
+        """(best_idx int64, best_period f64, best_power f64, status int32) per object."""
+        params = params or Params()
+        n_obj = cat.n_obj
+        dev = cat.offsets.device
+        if out is None:
+            out = (torch.empty(n_obj, dtype=torch.int64, device=dev),
+                   torch.empty(n_obj, dtype=torch.float64, device=dev),
+                   torch.empty(n_obj, dtype=torch.float64, device=dev),
+                   torch.empty(n_obj, dtype=torch.int32, device=dev))
+        bi, bp, bw, st = out
+        g = _Grid(float(grid[0]), float(grid[1]), int(grid[2]))
+        c = cat._c()
+        p = params._c()
+        _check(_lib.ss_best_period(self._h, int(method), ctypes.byref(c), ctypes.byref(g),
+                                   ctypes.byref(p), ctypes.c_void_p(bi.data_ptr()),
+                                   ctypes.c_void_p(bp.data_ptr()), ctypes.c_void_p(bw.data_ptr()),
+                                   ctypes.c_void_p(st.data_ptr()), _stream_ptr(stream)))
+        return bi, bp, bw, st

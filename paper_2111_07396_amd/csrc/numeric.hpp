@@ -1,0 +1,156 @@
+// Arithmetic policies of the trial kernel.
+//
+//   F64  : every per-point value and every prefix/window sum in FP64.
+//   F32C : per-point values in FP32; prefix and window sums as unevaluated
+//          float pairs (hi + lo, error-free transformations: Knuth's TwoSum,
+//          Dekker's Fast2Sum, FMA-based TwoProduct), i.e. compensated FP32
+//          summation carried through the parallel scan.  The phase keeps 48
+//          bits as an exact float pair.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "wave.hpp"
+
+namespace ssg {
+
+// 1/a for FP64: hardware estimate refined by two Newton steps (about one ulp).
+__device__ __forceinline__ double rcp64(double a) {
+    double r = __builtin_amdgcn_rcp(a);
+    double e = fma(-a, r, 1.0);
+    r = fma(e, r, r);
+    e = fma(-a, r, 1.0);
+    return fma(e, r, r);
+}
+
+// ------------------------------------------------------------------ float pairs
+struct df {
+    float hi, lo;
+};
+
+__device__ __forceinline__ df two_sum(float a, float b) {
+#pragma clang fp contract(off)
+    float s = a + b;
+    float bb = s - a;
+    float e = (a - (s - bb)) + (b - bb);
+    return {s, e};
+}
+
+__device__ __forceinline__ df fast_two_sum(float a, float b) {  // needs |a| >= |b| or a == 0
+#pragma clang fp contract(off)
+    float s = a + b;
+    float e = b - (s - a);
+    return {s, e};
+}
+
+__device__ __forceinline__ df two_prod(float a, float b) {
+#pragma clang fp contract(off)
+    float p = a * b;
+    float e = __builtin_fmaf(a, b, -p);
+    return {p, e};
+}
+
+// Pair sum with error about 2^-48 (|a| + |b|): enough for window sums taken
+// as differences of prefix sums.
+__device__ __forceinline__ df df_add(df a, df b) {
+#pragma clang fp contract(off)
+    df s = two_sum(a.hi, b.hi);
+    float e = s.lo + (a.lo + b.lo);
+    return fast_two_sum(s.hi, e);
+}
+
+__device__ __forceinline__ df df_neg(df a) { return {-a.hi, -a.lo}; }
+__device__ __forceinline__ df df_sub(df a, df b) { return df_add(a, df_neg(b)); }
+
+__device__ __forceinline__ df df_mul(df a, df b) {
+#pragma clang fp contract(off)
+    df p = two_prod(a.hi, b.hi);
+    float e = __builtin_fmaf(a.hi, b.lo, p.lo);
+    e = __builtin_fmaf(a.lo, b.hi, e);
+    return fast_two_sum(p.hi, e);
+}
+
+__device__ __forceinline__ df df_mul_f(df a, float b) {
+#pragma clang fp contract(off)
+    df p = two_prod(a.hi, b);
+    float e = __builtin_fmaf(a.lo, b, p.lo);
+    return fast_two_sum(p.hi, e);
+}
+
+template <int CTRL, int ROWMASK, bool BC>
+__device__ __forceinline__ df dpp_df(df v) {
+    return {dpp_f32<CTRL, ROWMASK, BC>(v.hi), dpp_f32<CTRL, ROWMASK, BC>(v.lo)};
+}
+
+__device__ __forceinline__ df wave_incl_sum_df(df x) {
+    x = df_add(x, dpp_df<0x111, 0xf, true>(x));
+    x = df_add(x, dpp_df<0x112, 0xf, true>(x));
+    x = df_add(x, dpp_df<0x114, 0xf, true>(x));
+    x = df_add(x, dpp_df<0x118, 0xf, true>(x));
+    x = df_add(x, dpp_df<0x142, 0xa, false>(x));
+    x = df_add(x, dpp_df<0x143, 0xc, false>(x));
+    return x;
+}
+
+// ------------------------------------------------------------------ policies
+struct F64 {
+    using R = double;  // per-point values
+    using S = double;  // prefix / window sums and the phase
+    static constexpr bool kIsF64 = true;
+    __device__ static S add(S a, S b) { return a + b; }
+    __device__ static S sub(S a, S b) { return a - b; }
+    __device__ static S neg(S a) { return -a; }
+    __device__ static S twice(S a) { return 2.0 * a; }
+    __device__ static S mul(S a, S b) { return a * b; }
+    __device__ static S mulr(S a, R b) { return a * b; }
+    __device__ static S prod(R a, R b) { return a * b; }
+    __device__ static S from(R a) { return a; }
+    __device__ static R real(S a) { return a; }
+    __device__ static double dbl(S a) { return a; }
+    __device__ static S zero() { return 0.0; }
+    __device__ static S quot(S a, S /*b*/, R ib) { return a * ib; }
+    __device__ static S scan(S x) { return wave_incl_sum(x); }
+    __device__ static R rcp(R a) { return rcp64(a); }
+    __device__ static R fabs_(R a) { return fabs(a); }
+    __device__ static S x_of_key(uint64_t key) { return (double)(key >> 16) * 0x1p-48; }
+    __device__ static R exp2_log2_pow(R t, R e) {
+        return (double)__builtin_amdgcn_exp2f((float)e * __builtin_amdgcn_logf((float)t));
+    }
+};
+
+struct F32C {
+    using R = float;
+    using S = df;
+    static constexpr bool kIsF64 = false;
+    __device__ static S add(S a, S b) { return df_add(a, b); }
+    __device__ static S sub(S a, S b) { return df_sub(a, b); }
+    __device__ static S neg(S a) { return df_neg(a); }
+    __device__ static S twice(S a) { return {2.0f * a.hi, 2.0f * a.lo}; }
+    __device__ static S mul(S a, S b) { return df_mul(a, b); }
+    __device__ static S mulr(S a, R b) { return df_mul_f(a, b); }
+    __device__ static S prod(R a, R b) { return two_prod(a, b); }
+    __device__ static S from(R a) { return {a, 0.0f}; }
+    __device__ static R real(S a) { return a.hi + a.lo; }
+    __device__ static double dbl(S a) { return (double)a.hi + (double)a.lo; }
+    __device__ static S zero() { return {0.0f, 0.0f}; }
+    // a/b to pair precision from an estimate of 1/b
+    __device__ static S quot(S a, S b, R ib) {
+        float q1 = a.hi * ib;
+        df r = df_sub(a, df_mul_f(b, q1));
+        float q2 = r.hi * ib;
+        return fast_two_sum(q1, q2);
+    }
+    __device__ static S scan(S x) { return wave_incl_sum_df(x); }
+    __device__ static R rcp(R a) { return __builtin_amdgcn_rcpf(a); }
+    __device__ static R fabs_(R a) { return fabsf(a); }
+    __device__ static S x_of_key(uint64_t key) {
+        uint64_t ph = key >> 16;  // 48-bit phase: exactly hi (top 24 bits) + lo
+        return fast_two_sum((float)(uint32_t)(ph >> 24) * 0x1p-24f,
+                            (float)(uint32_t)(ph & 0xffffffu) * 0x1p-48f);
+    }
+    __device__ static R exp2_log2_pow(R t, R e) {
+        return __builtin_amdgcn_exp2f(e * __builtin_amdgcn_logf(t));
+    }
+};
+
+}  // namespace ssg

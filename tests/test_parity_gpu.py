@@ -1,0 +1,174 @@
+"""GPU parity: the HIP path against the FP64 CPU oracle on the same seeded
+inputs, through the C ABI.  Tolerance (FP64 path): at every frequency
+|chi2_gpu - chi2_oracle| <= 1e-4 * chi2_oracle, i.e.
+|P_gpu - P_oracle| <= 1e-4 * (1 - P_oracle); the best index must be equal
+unless the oracle's two largest P differ by less than that tolerance."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2111_07396_amd as ssg
+from paper_2111_07396_amd import synth
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    c = ssg.Context(0)
+    yield c
+    c.close()
+
+
+def _gpu_pgram(ctx, method, offs, t, y, e, grid, params=None):
+    import torch
+    cat = ssg.DeviceCatalog.from_numpy(offs, t, y, e)
+    fn = ctx.ss_periodogram if method == oracle.SS else ctx.sssp_periodogram
+    pg, st = fn(cat, grid, params)
+    torch.cuda.synchronize()
+    return pg.cpu().numpy().astype(np.float64), st.cpu().numpy()
+
+
+def _assert_pgram_close(pg, po, tol=TOL, what=""):
+    ok = np.isfinite(po)
+    assert np.array_equal(ok, np.isfinite(pg)), what
+    d = np.abs(pg[ok] - po[ok])
+    lim = tol * np.maximum(1.0 - po[ok], 1e-12) + 1e-12
+    bad = d > lim
+    assert not bad.any(), f"{what}: {bad.sum()} of {bad.size} over tol, worst {np.max(d / lim)}"
+
+
+def _assert_best_equal(pg, po, tol=TOL):
+    for o in range(po.shape[0]):
+        if not np.isfinite(po[o]).any():
+            continue
+        ko, kg = oracle.best(po[o]), oracle.best(pg[o])
+        if ko == kg:
+            continue
+        top = np.sort(po[o][np.isfinite(po[o])])[::-1]
+        assert top[0] - top[1] < tol * (1 - top[0]), (o, ko, kg)
+
+
+@pytest.mark.parametrize("method", [oracle.SS, oracle.SSSP])
+def test_single_small_full_grid(ctx, method):
+    cat, grid = synth.single_small()
+    po, so = oracle.periodogram(method, cat.offsets, cat.t, cat.y, cat.e, *grid)
+    pg, sg = _gpu_pgram(ctx, method, cat.offsets, cat.t, cat.y, cat.e, grid)
+    assert np.array_equal(so, sg)
+    _assert_pgram_close(pg, po, what="single object N=100")
+    _assert_best_equal(pg, po)
+
+
+LENGTHS = [5, 6, 17, 63, 64, 65, 100, 128, 129, 191, 192, 193, 255, 256, 257, 300, 383, 384,
+           385, 450, 511, 512]
+
+
+@pytest.mark.parametrize("method", [oracle.SS, oracle.SSSP])
+def test_every_size_class_and_ragged_tile(ctx, method):
+    rng = np.random.default_rng(123)
+    cats = [synth.make_catalog(1000 + i, 1, n, 500.0, (0.3, 5.0), 0.05, shapes=(i % 3,))
+            for i, n in enumerate(LENGTHS)]
+    offs = np.concatenate([[0], np.cumsum([c.offsets[-1] for c in cats])]).astype(np.int64)
+    t = np.concatenate([c.t for c in cats])
+    y = np.concatenate([c.y for c in cats])
+    e = np.concatenate([c.e for c in cats]) * rng.uniform(0.5, 2.0, offs[-1])
+    grid = (0.2, 3.3, 173)  # not a multiple of any tile
+    po, so = oracle.periodogram(method, offs, t, y, e, *grid)
+    pg, sg = _gpu_pgram(ctx, method, offs, t, y, e, grid)
+    assert np.array_equal(so, sg)
+    _assert_pgram_close(pg, po, what="size classes")
+    _assert_best_equal(pg, po)
+
+
+@pytest.mark.parametrize("alpha", [0.0, 4.5, 9.0, 10.0])
+def test_alpha_and_fixed_span(ctx, alpha):
+    cat, grid = synth.catalog_uneven(seed=21, n_obj=6)
+    grid = (0.1, 10.0, 300)
+    prm = ssg.Params(alpha=alpha)
+    po, _ = oracle.periodogram(oracle.SS, cat.offsets, cat.t, cat.y, cat.e, *grid, alpha=alpha)
+    pg, _ = _gpu_pgram(ctx, oracle.SS, cat.offsets, cat.t, cat.y, cat.e, grid, prm)
+    _assert_pgram_close(pg, po, what=f"alpha={alpha}")
+    for method in (oracle.SS, oracle.SSSP):
+        po, _ = oracle.periodogram(method, cat.offsets, cat.t, cat.y, cat.e, *grid,
+                                   fixed_span=0.3)
+        pg, _ = _gpu_pgram(ctx, method, cat.offsets, cat.t, cat.y, cat.e, grid,
+                           ssg.Params(fixed_span=0.3))
+        _assert_pgram_close(pg, po, what=f"fixed span method={method}")
+
+
+def test_sinusoid_closed_form_on_gpu(ctx):
+    # t_j = j/64 d, f = 1 c/d: exact phases j/64; P has a closed form
+    from tests.test_oracle_pins import _ss_closed_form, _sinusoid_object
+    t, y, e = _sinusoid_object()
+    offs = np.array([0, t.size], dtype=np.int64)
+    pg, _ = _gpu_pgram(ctx, oracle.SS, offs, t, y, e, (1.0, 2.0, 4))
+    assert abs(pg[0, 0] - _ss_closed_form(9.0)) < 1e-12
+
+
+def test_statuses_and_nan_rows(ctx):
+    import torch
+    rng = np.random.default_rng(5)
+    lens = [0, 3, 40, 40, 40, 40, 80]
+    offs = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    t = rng.uniform(0, 100, offs[-1])
+    y = 15 + rng.normal(0, 0.1, offs[-1])
+    e = np.full(offs[-1], 0.1)
+    t[offs[2] + 5] = np.nan          # object 2: non-finite t
+    e[offs[3] + 7] = 0.0             # object 3: bad error
+    y[offs[4]:offs[5]] = 12.5        # object 4: constant
+    y[offs[5] + 1] = np.inf          # object 5: non-finite y
+    grid = (0.5, 2.0, 50)
+    for method in (oracle.SS, oracle.SSSP):
+        po, so = oracle.periodogram(method, offs, t, y, e, *grid)
+        pg, sg = _gpu_pgram(ctx, method, offs, t, y, e, grid)
+        assert list(sg) == [1, 1, 3, 2, 4, 3, 0]
+        assert np.array_equal(so, sg)
+        assert np.isnan(pg[:6]).all()
+        _assert_pgram_close(pg[6:], po[6:])
+        cat = ssg.DeviceCatalog.from_numpy(offs, t, y, e)
+        bi, bp, bw, st = ctx.ss_best_period(method, cat, grid)
+        bi = bi.cpu().numpy()
+        assert list(bi[:6]) == [-1] * 6
+        assert np.isnan(bp.cpu().numpy()[:6]).all()
+        assert bi[6] == oracle.best(po[6])
+
+
+def test_phase_ties(ctx):
+    # Dyadic times folded at power-of-two frequencies: both the oracle's
+    # (tt mod p)/p and the kernel's frac(tt f) are exact there, so the many
+    # equal phases are exact ties on both sides (tie averaging, windows with
+    # zero spread).  At other frequencies such ties are only ties up to the
+    # fold's rounding, and either order is a correct answer.
+    rng = np.random.default_rng(8)
+    t = np.sort(rng.choice(4096, 150, replace=False)) / 16.0
+    y = 15 + 0.2 * np.sin(2 * np.pi * t / 3.0) + rng.normal(0, 0.05, t.size)
+    e = rng.uniform(0.03, 0.08, t.size)
+    offs = np.array([0, t.size], dtype=np.int64)
+    for f in (0.125, 0.25, 0.5, 1.0, 2.0, 4.0):
+        grid = (f, 2 * f, 1)
+        for method in (oracle.SS, oracle.SSSP):
+            po, _ = oracle.periodogram(method, offs, t, y, e, *grid)
+            pg, _ = _gpu_pgram(ctx, method, offs, t, y, e, grid)
+            _assert_pgram_close(pg, po, what=f"ties f={f} method={method}")
+
+
+@pytest.mark.parametrize("method", [oracle.SS, oracle.SSSP])
+def test_best_period_matches_periodogram(ctx, method):
+    import torch
+    cat, _ = synth.catalog_uneven(seed=33, n_obj=40)
+    grid = (0.1, 10.0, 700)
+    dc = ssg.DeviceCatalog.from_numpy(cat.offsets, cat.t, cat.y, cat.e)
+    fn = ctx.ss_periodogram if method == oracle.SS else ctx.sssp_periodogram
+    pg, st = fn(dc, grid)
+    bi, bp, bw, st2 = ctx.ss_best_period(method, dc, grid)
+    torch.cuda.synchronize()
+    pg = pg.cpu().numpy()
+    bi = bi.cpu().numpy()
+    for o in range(cat.n_obj):
+        k = oracle.best(pg[o])
+        assert bi[o] == k
+        assert bw.cpu().numpy()[o] == pg[o, k]
+        f = oracle.freq(grid[0], grid[1], grid[2], k)
+        assert bp.cpu().numpy()[o] == 1.0 / f
