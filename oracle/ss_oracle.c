@@ -325,6 +325,7 @@ void ora_supsmu(int n, const double *x, const double *y, const double *w, int ip
     }
     for (int j = 0; j < n; ++j) {
         double resmin = 1.0e20;
+        sel[j] = 0.0; /* Listing 1 leaves it unset if no residual is below 1e20 */
         for (int k = 0; k < 3; ++k) {
             if (rt[k][j] < resmin) {
                 resmin = rt[k][j];

@@ -101,6 +101,7 @@ struct F64 {
     __device__ static S sub(S a, S b) { return a - b; }
     __device__ static S neg(S a) { return -a; }
     __device__ static S twice(S a) { return 2.0 * a; }
+    __device__ static S scale(S a, R q) { return a * q; }  // exact for q in {-1, 0, 1, 2}
     __device__ static S mul(S a, S b) { return a * b; }
     __device__ static S mulr(S a, R b) { return a * b; }
     __device__ static S prod(R a, R b) { return a * b; }
@@ -116,6 +117,26 @@ struct F64 {
     __device__ static R exp2_log2_pow(R t, R e) {
         return (double)__builtin_amdgcn_exp2f((float)e * __builtin_amdgcn_logf((float)t));
     }
+    // Window geometry: the local line through a window evaluated at x_j is
+    // linear in the window sums of w v and w x v: s = A Sv + B Sxv with
+    // B = (x_j - xm)/V (0 when V <= vsmlsq) and A = 1/W - xm B.  h is the
+    // leverage term 1/W + (x_j - xm)^2/V.
+    struct Geo {
+        double A, B;
+    };
+    __device__ static Geo geo(S W, S Sx, S Sxx, S xj, double vsmlsq, R &h) {
+        const double iW = rcp64(W);
+        const double xm = Sx * iW;
+        const double V = Sxx - Sx * xm;
+        const double iV = V > vsmlsq ? rcp64(V) : 0.0;
+        const double dx = xj - xm;
+        Geo g;
+        g.B = iV * dx;
+        g.A = iW - xm * g.B;
+        h = iW + dx * g.B;
+        return g;
+    }
+    __device__ static R eval(const Geo &g, S Sv, S Sxv) { return fma(g.A, Sv, g.B * Sxv); }
 };
 
 struct F32C {
@@ -126,6 +147,7 @@ struct F32C {
     __device__ static S sub(S a, S b) { return df_sub(a, b); }
     __device__ static S neg(S a) { return df_neg(a); }
     __device__ static S twice(S a) { return {2.0f * a.hi, 2.0f * a.lo}; }
+    __device__ static S scale(S a, R q) { return {a.hi * q, a.lo * q}; }  // q in {-1, 0, 1, 2}
     __device__ static S mul(S a, S b) { return df_mul(a, b); }
     __device__ static S mulr(S a, R b) { return df_mul_f(a, b); }
     __device__ static S prod(R a, R b) { return two_prod(a, b); }
@@ -150,6 +172,26 @@ struct F32C {
     }
     __device__ static R exp2_log2_pow(R t, R e) {
         return __builtin_amdgcn_exp2f(e * __builtin_amdgcn_logf(t));
+    }
+    // s = Sv/W + B (Sxv - xm Sv) with the covariance term formed in pair
+    // precision (it cancels heavily when the window sits far from x = 0).
+    struct Geo {
+        float iW, B;
+        df xm;
+    };
+    __device__ static Geo geo(S W, S Sx, S Sxx, S xj, double vsmlsq, R &h) {
+        Geo g;
+        g.iW = rcp(real(W));
+        g.xm = quot(Sx, W, g.iW);
+        const float V = real(df_sub(Sxx, df_mul(Sx, g.xm)));
+        const float iV = (double)V > vsmlsq ? rcp(V) : 0.0f;
+        const float dx = real(df_sub(xj, g.xm));
+        g.B = iV * dx;
+        h = g.iW + dx * g.B;
+        return g;
+    }
+    __device__ static R eval(const Geo &g, S Sv, S Sxv) {
+        return real(Sv) * g.iW + g.B * real(df_sub(Sxv, df_mul(g.xm, Sv)));
     }
 };
 
