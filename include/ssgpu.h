@@ -14,8 +14,10 @@
  *    the caller.  The library never frees or retains caller memory.
  *  - Calls are asynchronous on the HIP stream passed as `stream`
  *    (hipStream_t, NULL = the default stream).  Outputs are valid once that
- *    stream has been synchronized.  Planning reads the catalog offsets back
- *    to the host (8 bytes per object) with a synchronous copy on `stream`.
+ *    stream has been synchronized.  A call never synchronizes or reads device
+ *    data on the host: planning (shape classes, work queues) runs on the
+ *    device, so a call may be captured into a HIP graph and replayed, once a
+ *    first call with the same sizes has grown the context's workspace.
  *  - Return value: SS_OK (0) or a negative SS_ERR_* code.  Argument errors
  *    are detected before any work is enqueued; ss_last_error() returns a
  *    thread-local message for the last failing call.
@@ -46,7 +48,11 @@ extern "C" {
 #define SS_OBJ_BAD_ERR 2    /* an error bar e <= 0 or non-finite */
 #define SS_OBJ_NONFINITE 3  /* a non-finite t or y */
 #define SS_OBJ_CONST_MAG 4  /* chi0 == 0: constant magnitudes */
-/* Precedence when several apply: TOO_FEW, NONFINITE, BAD_ERR, CONST_MAG. */
+#define SS_OBJ_TOO_LONG 5   /* more than SS_MAX_POINTS points, or too long for the
+                               LDS of one trial group at the requested spans */
+#define SS_OBJ_BAD_RANGE 6  /* its offsets are decreasing or fall outside [0, n_points] */
+/* Precedence when several apply: BAD_RANGE, TOO_FEW, NONFINITE, BAD_ERR, CONST_MAG,
+ * TOO_LONG. */
 
 /* ---- precision (ss_params.precision) */
 #define SS_FP64 0  /* every sum and fit in FP64; periodogram is double */
@@ -90,10 +96,13 @@ typedef struct {
 
 /* A catalog of light curves in CSR form (device memory, FP64):
  * object o owns points offsets[o] .. offsets[o+1]-1 of t (days), y
- * (magnitudes) and e (error bars).  offsets[0] == 0, non-decreasing, n_obj+1
- * entries.  Points need not be time-sorted. */
+ * (magnitudes) and e (error bars); offsets has n_obj+1 entries and n_points
+ * is the length of t, y and e (normally offsets[n_obj]).  The library sizes
+ * its workspace from n_points and never reads offsets on the host.  Points
+ * need not be time-sorted. */
 typedef struct {
     int64_t n_obj;
+    int64_t n_points;
     const int64_t *offsets;
     const double *t;
     const double *y;
@@ -129,6 +138,21 @@ int sssp_periodogram(ss_ctx *ctx, const ss_catalog *cat, const ss_grid *grid,
 int ss_best_period(ss_ctx *ctx, int32_t method, const ss_catalog *cat, const ss_grid *grid,
                    const ss_params *params, int64_t *best_idx, double *best_period,
                    double *best_power, int32_t *obj_status, void *stream);
+
+/* Trial-group shapes (autotuning).  One trial runs on a workgroup of `nw`
+ * wavefronts whose threads hold `ppl` consecutive phase-sorted points each,
+ * so a shape holds light curves of up to 64*nw*ppl points.  ss_num_shapes /
+ * ss_shape_info list the shapes the library is built with.
+ * ss_ctx_set_shape(ctx, n_max, nw, ppl) adds a rule: objects with
+ * n <= n_max (and above the n_max of every smaller rule) run on that shape;
+ * objects no rule covers use the built-in default.  nw = 0 clears every rule.
+ * Returns SS_ERR_UNSUPPORTED for a shape that is not built in or holds fewer
+ * than n_max points.  ss_ctx_set_tile sets the number of trial frequencies
+ * per work item (0 = automatic). */
+int ss_num_shapes(void);
+int ss_shape_info(int index, int32_t *nw, int32_t *ppl);
+int ss_ctx_set_shape(ss_ctx *ctx, int32_t n_max, int32_t nw, int32_t ppl);
+int ss_ctx_set_tile(ss_ctx *ctx, int32_t tile_f);
 
 /* Kernel timing, for benchmarks.  With timing enabled, every call records HIP
  * events on its stream around each launch of the fused trial kernel (all size

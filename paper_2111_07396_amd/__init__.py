@@ -22,11 +22,24 @@ SS_ERR_INVALID_ARG, SS_ERR_HIP, SS_ERR_OOM, SS_ERR_UNSUPPORTED = -1, -2, -3, -4
 SS_FP64, SS_FP32C = 0, 1
 SS_METHOD_SS, SS_METHOD_SSSP = 0, 1
 OBJ_OK, OBJ_TOO_FEW, OBJ_BAD_ERR, OBJ_NONFINITE, OBJ_CONST_MAG = 0, 1, 2, 3, 4
+OBJ_TOO_LONG, OBJ_BAD_RANGE = 5, 6
 MAX_POINTS = 4096
 
 EXPORTED = ("ss_params_default", "ss_ctx_create", "ss_ctx_destroy", "ss_periodogram",
-            "sssp_periodogram", "ss_best_period", "ss_ctx_set_timing", "ss_ctx_trial_kernel_ms",
+            "sssp_periodogram", "ss_best_period", "ss_num_shapes", "ss_shape_info",
+            "ss_ctx_set_shape", "ss_ctx_set_tile", "ss_ctx_set_timing", "ss_ctx_trial_kernel_ms",
             "ss_last_error", "ss_version")
+
+
+def shapes():
+    """[(nw, ppl), ...] trial-group shapes built into the library."""
+    lib = load_library()
+    out = []
+    for i in range(lib.ss_num_shapes()):
+        nw, ppl = ctypes.c_int32(), ctypes.c_int32()
+        lib.ss_shape_info(i, ctypes.byref(nw), ctypes.byref(ppl))
+        out.append((nw.value, ppl.value))
+    return out
 
 
 class SSError(RuntimeError):
@@ -48,7 +61,8 @@ class _Params(ctypes.Structure):
 
 
 class _Catalog(ctypes.Structure):
-    _fields_ = [("n_obj", ctypes.c_int64), ("offsets", ctypes.c_void_p),
+    _fields_ = [("n_obj", ctypes.c_int64), ("n_points", ctypes.c_int64),
+                ("offsets", ctypes.c_void_p),
                 ("t", ctypes.c_void_p), ("y", ctypes.c_void_p), ("e", ctypes.c_void_p)]
 
 
@@ -78,6 +92,14 @@ def load_library(path: str = LIB_PATH):
     lib.ss_best_period.argtypes = [vp, i32, ctypes.POINTER(_Catalog), ctypes.POINTER(_Grid),
                                    ctypes.POINTER(_Params), vp, vp, vp, vp, vp]
     lib.ss_best_period.restype = ctypes.c_int
+    lib.ss_num_shapes.argtypes = []
+    lib.ss_num_shapes.restype = ctypes.c_int
+    lib.ss_shape_info.argtypes = [ctypes.c_int, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    lib.ss_shape_info.restype = ctypes.c_int
+    lib.ss_ctx_set_shape.argtypes = [vp, i32, i32, i32]
+    lib.ss_ctx_set_shape.restype = ctypes.c_int
+    lib.ss_ctx_set_tile.argtypes = [vp, i32]
+    lib.ss_ctx_set_tile.restype = ctypes.c_int
     lib.ss_ctx_set_timing.argtypes = [vp, ctypes.c_int]
     lib.ss_ctx_set_timing.restype = ctypes.c_int
     lib.ss_ctx_trial_kernel_ms.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
@@ -136,7 +158,9 @@ class DeviceCatalog:
             if a.dtype != dt or not a.is_cuda or not a.is_contiguous():
                 raise ValueError("catalog tensors must be contiguous CUDA tensors "
                                  "(offsets int64; t, y, e float64)")
-        return _Catalog(self.n_obj, self.offsets.data_ptr(), self.t.data_ptr(),
+        if not (self.t.numel() == self.y.numel() == self.e.numel()):
+            raise ValueError("t, y and e must have the same length")
+        return _Catalog(self.n_obj, self.t.numel(), self.offsets.data_ptr(), self.t.data_ptr(),
                         self.y.data_ptr(), self.e.data_ptr())
 
 
@@ -164,6 +188,15 @@ class Context:
             self.close()
         except Exception:
             pass
+
+    def set_shape(self, n_max: int, nw: int, ppl: int):
+        """Objects with n <= n_max run on trial groups of nw waves x ppl points per thread
+        (nw = 0 clears every rule)."""
+        _check(_lib.ss_ctx_set_shape(self._h, int(n_max), int(nw), int(ppl)))
+
+    def set_tile(self, tile_f: int):
+        """Trial frequencies per work item (0 = automatic)."""
+        _check(_lib.ss_ctx_set_tile(self._h, int(tile_f)))
 
     def set_timing(self, enable: bool = True):
         """Record HIP events around the fused trial-kernel launches of each call."""

@@ -12,19 +12,20 @@
 #include "ssgpu_internal.hpp"
 
 namespace ssg {
-hipError_t launch_trials_fp64(int cls, const TrialLaunch &L, hipStream_t s);
-hipError_t launch_trials_fp32c(int cls, const TrialLaunch &L, hipStream_t s);
 
-int class_of_length(int64_t n) {
-    for (int c = 0; c < kNumClasses; ++c)
-        if (n <= 64 * kClassPPL[c]) return c;
+// Default trial-group shape for a light curve of n points: the smallest
+// listed shape that holds it.
+int default_shape(int64_t n) {
+    static const int order[][3] = {{64, 1, 1},    {128, 1, 2},  {256, 2, 2},   {384, 2, 3},
+                                   {512, 4, 2},   {1024, 4, 4}, {2048, 8, 4},  {3072, 16, 3},
+                                   {4096, 16, 4}};
+    for (const auto &o : order)
+        if (n <= o[0])
+            for (int s = 0; s < kNumShapes; ++s)
+                if (kShapes[s].nw == o[1] && kShapes[s].ppl == o[2]) return s;
     return -1;
 }
 
-hipError_t launch_trials(int cls, int precision, const TrialLaunch &L, hipStream_t stream) {
-    return precision == SS_FP64 ? launch_trials_fp64(cls, L, stream)
-                                : launch_trials_fp32c(cls, L, stream);
-}
 }  // namespace ssg
 
 using namespace ssg;
@@ -66,11 +67,13 @@ struct DevBuf {
 
 struct ss_ctx {
     int device = 0;
-    DevBuf tt, w, yc, w32, yc32, chi0, objs, part_p, part_k, status;
-    std::vector<int64_t> h_offsets;
-    std::vector<int32_t> h_objs;
+    DevBuf tt, w, yc, w32, yc32, chi0, objs, counts, queues, part_p, part_k;
+    int max_lds = 65536;
+    int n_cu = 1;
+    std::vector<std::pair<int32_t, int>> rules;  // (n_max, shape index), sorted by n_max
+    int32_t tile_f = 0;
     bool timing = false;
-    hipEvent_t ev[2 * kNumClasses] = {};
+    hipEvent_t ev[2 * kNumShapes] = {};
     int n_timed = 0;
 };
 
@@ -90,6 +93,7 @@ int check_common(ss_ctx *ctx, const ss_catalog *cat, const ss_grid *grid, const 
     if (cat->n_obj > 0 && (!cat->offsets || !cat->t || !cat->y || !cat->e))
         return fail(SS_ERR_INVALID_ARG, "null catalog pointer");
     if (cat->n_obj > INT32_MAX) return fail(SS_ERR_INVALID_ARG, "n_obj too large");
+    if (cat->n_points < 0) return fail(SS_ERR_INVALID_ARG, "n_points < 0");
     if (!(grid->n_freq >= 1) || grid->n_freq > INT32_MAX)
         return fail(SS_ERR_INVALID_ARG, "n_freq must be in [1, 2^31)");
     if (!(std::isfinite(grid->f_min) && std::isfinite(grid->f_max) && grid->f_min > 0.0 &&
@@ -116,8 +120,9 @@ int32_t choose_tile(int64_t n_obj, int64_t n_freq) {
     return (int32_t)std::min<int64_t>(t, n_freq);
 }
 
-// Runs prep and every size class.  pgram64/pgram32 and the partial arrays may
-// be null independently.
+// Runs reset, prep (with device-side planning), one persistent trial launch
+// per shape class that can receive objects, and the finalize step.  Nothing
+// here waits for the device.
 int run(ss_ctx *ctx, int method, const ss_catalog *cat, const ss_grid *grid,
         const ss_params *prm, double *pgram64, float *pgram32, bool want_best,
         int32_t *obj_status, hipStream_t stream, int64_t *best_idx, double *best_period,
@@ -125,38 +130,38 @@ int run(ss_ctx *ctx, int method, const ss_catalog *cat, const ss_grid *grid,
     const int64_t n_obj = cat->n_obj;
     if (n_obj == 0) return SS_OK;
     SS_HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
-
-    // ---- plan on the host: object lengths from the offsets
-    ctx->h_offsets.resize((size_t)n_obj + 1);
-    SS_HIP_TRY(hipMemcpyAsync(ctx->h_offsets.data(), cat->offsets, (size_t)(n_obj + 1) * 8,
-                              hipMemcpyDeviceToHost, stream),
-               "offsets to host");
-    SS_HIP_TRY(hipStreamSynchronize(stream), "offsets to host");
-    const int64_t *off = ctx->h_offsets.data();
-    if (off[0] != 0) return fail(SS_ERR_INVALID_ARG, "offsets[0] must be 0");
-    std::vector<int64_t> cls_count(kNumClasses, 0);
-    ctx->h_objs.resize((size_t)n_obj);
-    for (int64_t o = 0; o < n_obj; ++o) {
-        int64_t n = off[o + 1] - off[o];
-        if (n < 0) return fail(SS_ERR_INVALID_ARG, "offsets must be non-decreasing");
-        if (n > SS_MAX_POINTS)
-            return fail(SS_ERR_UNSUPPORTED, "object longer than SS_MAX_POINTS");
-        int c = class_of_length(n);
-        if (c < 0) return fail(SS_ERR_UNSUPPORTED, "object too long for the single-wave classes");
-        cls_count[c]++;
-    }
-    std::vector<int64_t> cls_start(kNumClasses + 1, 0);
-    for (int c = 0; c < kNumClasses; ++c) cls_start[c + 1] = cls_start[c] + cls_count[c];
-    {
-        std::vector<int64_t> fill(cls_start.begin(), cls_start.end() - 1);
-        for (int64_t o = 0; o < n_obj; ++o) {
-            int c = class_of_length(off[o + 1] - off[o]);
-            ctx->h_objs[(size_t)fill[c]++] = (int32_t)o;
-        }
-    }
-    const int64_t total = off[n_obj];
-    const int32_t tile = choose_tile(n_obj, grid->n_freq);
+    const int64_t total = cat->n_points;
+    const int32_t tile = ctx->tile_f > 0 ? (int32_t)std::min<int64_t>(ctx->tile_f, grid->n_freq)
+                                         : choose_tile(n_obj, grid->n_freq);
     const int32_t n_tiles = (int32_t)((grid->n_freq + tile - 1) / tile);
+
+    // ---- shape classes: rules, defaults, and which shapes fit in LDS
+    const double span_hi = std::max(prm->span_max, prm->fixed_span);
+    ShapeRules R{};
+    R.max_points = SS_MAX_POINTS;
+    R.n_rules = (int32_t)std::min<size_t>(ctx->rules.size(), 16);
+    for (int i = 0; i < R.n_rules; ++i) {
+        R.rule_n[i] = ctx->rules[(size_t)i].first;
+        R.rule_shape[i] = ctx->rules[(size_t)i].second;
+    }
+    for (int64_t nmax : {64, 128, 256, 384, 512, 1024, 2048, 3072, 4096}) {
+        R.def_n[R.n_def] = (int32_t)nmax;
+        R.def_shape[R.n_def] = default_shape(nmax);
+        R.n_def++;
+    }
+    std::vector<int32_t> ext(kNumShapes, 2);
+    std::vector<bool> used(kNumShapes, false);
+    R.runnable = 0u;
+    for (int c = 0; c < kNumShapes; ++c) {
+        const int np = 64 * kShapes[c].nw * kShapes[c].ppl;
+        ext[c] = std::max(2, trial_halfwidth(np, span_hi));
+        if (trial_lds_bytes(kShapes[c].nw, kShapes[c].ppl, ext[c]) <= ctx->max_lds)
+            R.runnable |= 1u << c;
+    }
+    R.fallback = default_shape(64);
+    for (int i = 0; i < R.n_rules; ++i) used[R.rule_shape[i]] = true;
+    for (int i = 0; i < R.n_def; ++i) used[R.def_shape[i]] = true;
+    used[R.fallback] = true;
 
     SS_HIP_TRY(ctx->tt.ensure((size_t)total * 8), "workspace");
     SS_HIP_TRY(ctx->w.ensure((size_t)total * 8), "workspace");
@@ -164,18 +169,20 @@ int run(ss_ctx *ctx, int method, const ss_catalog *cat, const ss_grid *grid,
     SS_HIP_TRY(ctx->w32.ensure((size_t)total * 4), "workspace");
     SS_HIP_TRY(ctx->yc32.ensure((size_t)total * 4), "workspace");
     SS_HIP_TRY(ctx->chi0.ensure((size_t)n_obj * 8), "workspace");
-    SS_HIP_TRY(ctx->objs.ensure((size_t)n_obj * 4), "workspace");
+    SS_HIP_TRY(ctx->objs.ensure((size_t)n_obj * kNumShapes * 4), "workspace");
+    SS_HIP_TRY(ctx->counts.ensure((size_t)kNumShapes * 4), "workspace");
+    SS_HIP_TRY(ctx->queues.ensure((size_t)kNumShapes * 8), "workspace");
     if (want_best) {
         SS_HIP_TRY(ctx->part_p.ensure((size_t)n_obj * n_tiles * 8), "workspace");
         SS_HIP_TRY(ctx->part_k.ensure((size_t)n_obj * n_tiles * 4), "workspace");
     }
-    SS_HIP_TRY(hipMemcpyAsync(ctx->objs.p, ctx->h_objs.data(), (size_t)n_obj * 4,
-                              hipMemcpyHostToDevice, stream),
-               "object lists to device");
-
-    SS_HIP_TRY(launch_prep(cat->offsets, cat->t, cat->y, cat->e, n_obj, (double *)ctx->tt.p,
-                           (double *)ctx->w.p, (double *)ctx->yc.p, (float *)ctx->w32.p,
-                           (float *)ctx->yc32.p, (double *)ctx->chi0.p, obj_status, stream),
+    int32_t *counts = (int32_t *)ctx->counts.p;
+    unsigned long long *queues = (unsigned long long *)ctx->queues.p;
+    SS_HIP_TRY(launch_reset(counts, queues, kNumShapes, stream), "reset kernel");
+    SS_HIP_TRY(launch_prep(cat->offsets, cat->t, cat->y, cat->e, n_obj, total,
+                           (double *)ctx->tt.p, (double *)ctx->w.p, (double *)ctx->yc.p,
+                           (float *)ctx->w32.p, (float *)ctx->yc32.p, (double *)ctx->chi0.p,
+                           obj_status, R, (int32_t *)ctx->objs.p, counts, stream),
                "prep kernel");
 
     TrialLaunch L{};
@@ -203,14 +210,18 @@ int run(ss_ctx *ctx, int method, const ss_catalog *cat, const ss_grid *grid,
     L.part_p = want_best ? (double *)ctx->part_p.p : nullptr;
     L.part_k = want_best ? (int32_t *)ctx->part_k.p : nullptr;
     ctx->n_timed = 0;
-    for (int c = 0; c < kNumClasses; ++c) {
-        if (cls_count[c] == 0) continue;
+    for (int c = 0; c < kNumShapes; ++c) {
+        if (!used[c] || !((R.runnable >> c) & 1u)) continue;
         TrialLaunch Lc = L;
-        Lc.objs = (const int32_t *)ctx->objs.p + cls_start[c];
-        Lc.n_items = cls_count[c] * n_tiles;
+        Lc.objs = (const int32_t *)ctx->objs.p + (int64_t)c * n_obj;
+        Lc.count = counts + c;
+        Lc.queue = queues + c;
+        Lc.ext = ext[c];
         if (ctx->timing)
             SS_HIP_TRY(hipEventRecord(ctx->ev[2 * ctx->n_timed], stream), "timing event");
-        SS_HIP_TRY(launch_trials(c, prm->precision, Lc, stream), "trial kernel");
+        SS_HIP_TRY(launch_trials(shape_id(kShapes[c].nw, kShapes[c].ppl), prm->precision, Lc,
+                                 n_obj * (int64_t)n_tiles, ctx->n_cu, stream),
+                   "trial kernel");
         if (ctx->timing) {
             SS_HIP_TRY(hipEventRecord(ctx->ev[2 * ctx->n_timed + 1], stream), "timing event");
             ctx->n_timed++;
@@ -249,6 +260,15 @@ int ss_ctx_create(int device, ss_ctx **out) {
     if (device < 0 || device >= count) return fail(SS_ERR_INVALID_ARG, "no such device");
     ss_ctx *c = new ss_ctx();
     c->device = device;
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) ==
+            hipSuccess &&
+        lds > 0)
+        c->max_lds = lds;
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
+        ncu > 0)
+        c->n_cu = ncu;
     *out = c;
     return SS_OK;
 }
@@ -265,7 +285,8 @@ void ss_ctx_destroy(ss_ctx *ctx) {
     ctx->objs.release();
     ctx->part_p.release();
     ctx->part_k.release();
-    ctx->status.release();
+    ctx->counts.release();
+    ctx->queues.release();
     if (ctx->timing)
         for (auto &e : ctx->ev) (void)hipEventDestroy(e);
     delete ctx;
@@ -306,6 +327,44 @@ int ss_best_period(ss_ctx *ctx, int32_t method, const ss_catalog *cat, const ss_
         return fail(SS_ERR_INVALID_ARG, "null output pointer");
     return run(ctx, method, cat, grid, params, nullptr, nullptr, true, obj_status,
                (hipStream_t)stream, best_idx, best_period, best_power);
+}
+
+int ss_num_shapes(void) { return kNumShapes; }
+
+int ss_shape_info(int index, int32_t *nw, int32_t *ppl) {
+    if (index < 0 || index >= kNumShapes || !nw || !ppl)
+        return fail(SS_ERR_INVALID_ARG, "bad shape index");
+    *nw = kShapes[index].nw;
+    *ppl = kShapes[index].ppl;
+    return SS_OK;
+}
+
+int ss_ctx_set_shape(ss_ctx *ctx, int32_t n_max, int32_t nw, int32_t ppl) {
+    if (!ctx) return fail(SS_ERR_INVALID_ARG, "null context");
+    if (nw == 0) {
+        ctx->rules.clear();
+        return SS_OK;
+    }
+    int idx = -1;
+    for (int s = 0; s < kNumShapes; ++s)
+        if (kShapes[s].nw == nw && kShapes[s].ppl == ppl) idx = s;
+    if (idx < 0) return fail(SS_ERR_UNSUPPORTED, "shape not built in");
+    if (n_max < 1 || n_max > 64 * nw * ppl || n_max > SS_MAX_POINTS)
+        return fail(SS_ERR_UNSUPPORTED, "shape too small for n_max");
+    for (auto &r : ctx->rules)
+        if (r.first == n_max) {
+            r.second = idx;
+            return SS_OK;
+        }
+    ctx->rules.emplace_back(n_max, idx);
+    std::sort(ctx->rules.begin(), ctx->rules.end());
+    return SS_OK;
+}
+
+int ss_ctx_set_tile(ss_ctx *ctx, int32_t tile_f) {
+    if (!ctx || tile_f < 0) return fail(SS_ERR_INVALID_ARG, "bad tile");
+    ctx->tile_f = tile_f;
+    return SS_OK;
 }
 
 int ss_ctx_set_timing(ss_ctx *ctx, int enable) {

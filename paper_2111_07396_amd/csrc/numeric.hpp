@@ -23,6 +23,8 @@ __device__ __forceinline__ double rcp64(double a) {
     return fma(e, r, r);
 }
 
+
+
 // ------------------------------------------------------------------ float pairs
 struct df {
     float hi, lo;
@@ -77,6 +79,10 @@ __device__ __forceinline__ df df_mul_f(df a, float b) {
     return fast_two_sum(p.hi, e);
 }
 
+__device__ __forceinline__ df readlane_df(df v, int lane) {
+    return {readlane_f32(v.hi, lane), readlane_f32(v.lo, lane)};
+}
+
 template <int CTRL, int ROWMASK, bool BC>
 __device__ __forceinline__ df dpp_df(df v) {
     return {dpp_f32<CTRL, ROWMASK, BC>(v.hi), dpp_f32<CTRL, ROWMASK, BC>(v.lo)};
@@ -111,6 +117,7 @@ struct F64 {
     __device__ static S zero() { return 0.0; }
     __device__ static S quot(S a, S /*b*/, R ib) { return a * ib; }
     __device__ static S scan(S x) { return wave_incl_sum(x); }
+    __device__ static S lane_value(S x, int lane) { return readlane_f64(x, lane); }
     __device__ static R rcp(R a) { return rcp64(a); }
     __device__ static R fabs_(R a) { return fabs(a); }
     __device__ static S x_of_key(uint64_t key) { return (double)(key >> 16) * 0x1p-48; }
@@ -163,6 +170,7 @@ struct F32C {
         return fast_two_sum(q1, q2);
     }
     __device__ static S scan(S x) { return wave_incl_sum_df(x); }
+    __device__ static S lane_value(S x, int lane) { return readlane_df(x, lane); }
     __device__ static R rcp(R a) { return __builtin_amdgcn_rcpf(a); }
     __device__ static R fabs_(R a) { return fabsf(a); }
     __device__ static S x_of_key(uint64_t key) {

@@ -8,66 +8,88 @@ namespace {
 
 constexpr int kPrepWaves = 4;
 
+__device__ __forceinline__ int pick_shape(const ShapeRules &R, int64_t n) {
+    for (int i = 0; i < R.n_rules; ++i)
+        if (n <= R.rule_n[i]) return R.rule_shape[i];
+    for (int i = 0; i < R.n_def; ++i)
+        if (n <= R.def_n[i]) return R.def_shape[i];
+    return -1;
+}
+
+__global__ void reset_kernel(int32_t *counts, unsigned long long *queues, int n) {
+    const int i = threadIdx.x;
+    if (i < n) {
+        counts[i] = 0;
+        queues[i] = 0ull;
+    }
+}
+
 // One wavefront per object.  FP64 throughout.  Status precedence: fewer than
-// 5 points, non-finite t or y, bad error bar, chi0 == 0.
+// 5 points, non-finite t or y, bad error bar, chi0 == 0, too long.  Lane 0
+// then files the object in its shape class.
 __global__ __launch_bounds__(kWave *kPrepWaves) void prep_kernel(
     const int64_t *__restrict__ offsets, const double *__restrict__ t,
-    const double *__restrict__ y, const double *__restrict__ e, int64_t n_obj,
+    const double *__restrict__ y, const double *__restrict__ e, int64_t n_obj, int64_t n_points,
     double *__restrict__ tt, double *__restrict__ w, double *__restrict__ yc,
     float *__restrict__ w32, float *__restrict__ yc32, double *__restrict__ chi0,
-    int32_t *__restrict__ status) {
+    int32_t *__restrict__ status, ShapeRules rules, int32_t *__restrict__ objs,
+    int32_t *__restrict__ counts) {
     const int lane = threadIdx.x % kWave;
     const int64_t obj = (int64_t)blockIdx.x * kPrepWaves + threadIdx.x / kWave;
     if (obj >= n_obj) return;
     const int64_t a = offsets[obj], n = offsets[obj + 1] - a;
-    if (n < 5) {
-        if (lane == 0) {
-            status[obj] = 1;
-            chi0[obj] = __builtin_nan("");
+    int32_t st = 0;
+    double c0 = __builtin_nan("");
+    if (a < 0 || n < 0 || a + n > n_points) {
+        st = 6;
+    } else if (n < 5) {
+        st = 1;
+    } else {
+        bool nonfinite = false, baderr = false;
+        double tmin = __builtin_inf(), sw = 0.0, swy = 0.0;
+        for (int64_t i = lane; i < n; i += kWave) {
+            const double ti = t[a + i], yi = y[a + i], ei = e[a + i];
+            nonfinite |= !__builtin_isfinite(ti) || !__builtin_isfinite(yi);
+            baderr |= !__builtin_isfinite(ei) || !(ei > 0.0);
+            tmin = fmin(tmin, ti);
+            const double wi = 1.0 / (ei * ei);
+            sw += wi;
+            swy += wi * yi;
         }
-        return;
-    }
-    bool nonfinite = false, baderr = false;
-    double tmin = __builtin_inf(), sw = 0.0, swy = 0.0;
-    for (int64_t i = lane; i < n; i += kWave) {
-        double ti = t[a + i], yi = y[a + i], ei = e[a + i];
-        nonfinite |= !__builtin_isfinite(ti) || !__builtin_isfinite(yi);
-        baderr |= !__builtin_isfinite(ei) || !(ei > 0.0);
-        tmin = fmin(tmin, ti);
-        double wi = 1.0 / (ei * ei);
-        sw += wi;
-        swy += wi * yi;
-    }
-    nonfinite = wave_ballot(nonfinite) != 0;
-    baderr = wave_ballot(baderr) != 0;
-    int32_t st = nonfinite ? 3 : (baderr ? 2 : 0);
-    if (st != 0) {
-        if (lane == 0) {
-            status[obj] = st;
-            chi0[obj] = __builtin_nan("");
+        nonfinite = wave_ballot(nonfinite) != 0;
+        baderr = wave_ballot(baderr) != 0;
+        st = nonfinite ? 3 : (baderr ? 2 : 0);
+        if (st == 0) {
+            tmin = wave_min(tmin);
+            sw = wave_sum(sw);
+            swy = wave_sum(swy);
+            const double ybar = swy / sw;
+            double acc = 0.0;
+            for (int64_t i = lane; i < n; i += kWave) {
+                const double ei = e[a + i];
+                const double wi = 1.0 / (ei * ei);
+                const double d = y[a + i] - ybar;
+                acc += wi * d * d;
+                tt[a + i] = t[a + i] - tmin;
+                w[a + i] = wi;
+                yc[a + i] = d;
+                w32[a + i] = (float)wi;
+                yc32[a + i] = (float)d;
+            }
+            c0 = wave_sum(acc);
+            if (!(c0 > 0.0)) st = 4;
         }
-        return;
     }
-    tmin = wave_min(tmin);
-    sw = wave_sum(sw);
-    swy = wave_sum(swy);
-    const double ybar = swy / sw;
-    double c0 = 0.0;
-    for (int64_t i = lane; i < n; i += kWave) {
-        double ei = e[a + i];
-        double wi = 1.0 / (ei * ei);
-        double d = y[a + i] - ybar;
-        c0 += wi * d * d;
-        tt[a + i] = t[a + i] - tmin;
-        w[a + i] = wi;
-        yc[a + i] = d;
-        w32[a + i] = (float)wi;
-        yc32[a + i] = (float)d;
-    }
-    c0 = wave_sum(c0);
     if (lane == 0) {
-        status[obj] = (c0 > 0.0) ? 0 : 4;
+        int cls = (st != 6 && n >= 1) ? pick_shape(rules, n) : rules.fallback;
+        if (st != 6 && (n > rules.max_points || cls < 0 || !((rules.runnable >> cls) & 1u))) {
+            if (st == 0) st = 5;
+            cls = rules.fallback;
+        }
+        status[obj] = st;
         chi0[obj] = c0;
+        const int32_t slot = atomicAdd(&counts[cls], 1);
+        objs[(int64_t)cls * n_obj + slot] = (int32_t)obj;
     }
 }
 
@@ -108,13 +130,21 @@ __global__ void finalize_kernel(const double *__restrict__ part_p,
 
 }  // namespace
 
+hipError_t launch_reset(int32_t *counts, unsigned long long *queues, int n, hipStream_t stream) {
+    hipLaunchKernelGGL(reset_kernel, dim3(1), dim3(64), 0, stream, counts, queues, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_prep(const int64_t *offsets, const double *t, const double *y, const double *e,
-                       int64_t n_obj, double *tt, double *w, double *yc, float *w32, float *yc32,
-                       double *chi0, int32_t *status, hipStream_t stream) {
+                       int64_t n_obj, int64_t n_points, double *tt, double *w, double *yc, float *w32, float *yc32,
+                       double *chi0, int32_t *status, const ShapeRules &rules, int32_t *objs,
+                       int32_t *counts, hipStream_t stream) {
     if (n_obj <= 0) return hipSuccess;
     const int64_t blocks = (n_obj + kPrepWaves - 1) / kPrepWaves;
     hipLaunchKernelGGL(prep_kernel, dim3((unsigned)blocks), dim3(kWave * kPrepWaves), 0, stream,
-                       offsets, t, y, e, n_obj, tt, w, yc, w32, yc32, chi0, status);
+                       offsets, t, y, e, n_obj, n_points, tt, w, yc, w32, yc32, chi0, status, rules,
+                       objs,
+                       counts);
     return hipGetLastError();
 }
 

@@ -17,11 +17,14 @@ struct Prepared {
     const int32_t *status;   // per object
 };
 
-// One launch of the trial kernel over one size class.
+// One persistent launch of the trial kernel over one shape class.  Work items
+// are (object of the class, frequency tile); workgroups take them from a
+// device-side queue until count * n_tiles items are done.
 struct TrialLaunch {
     Prepared cat;
-    const int32_t *objs;  // object ids of this class
-    int64_t n_items;      // objects_in_class * n_tiles
+    const int32_t *objs;         // object ids of this class (written by prep)
+    const int32_t *count;        // number of objects in this class
+    unsigned long long *queue;   // next item to hand out (zeroed before prep)
     int32_t n_tiles;
     int32_t tile_f;
     double fmin, df;
@@ -30,6 +33,7 @@ struct TrialLaunch {
     double alpha;
     double fixed_span;
     int32_t method;       // 0 SS, 1 SSSP
+    int32_t ext;          // periodic extension of the prefix sums (>= every b used)
     double *pgram64;      // [n_obj * n_freq] or null
     float *pgram32;       // [n_obj * n_freq] or null
     double *part_p;       // [n_obj * n_tiles] or null
@@ -39,35 +43,68 @@ struct TrialLaunch {
 // Expressions that must round exactly like their plain C statement (no
 // fused multiply-add), so that grid frequencies, window half-widths and the
 // Listing 1 threshold agree bit for bit with a straightforward evaluation.
-__device__ __forceinline__ double grid_freq(double fmin, double df, int64_t k) {
+__host__ __device__ __forceinline__ double grid_freq(double fmin, double df, int64_t k) {
 #pragma clang fp contract(off)
     double kd = (double)k;
     double step = kd * df;
     return fmin + step;
 }
 
-__device__ __forceinline__ double halfwidth_real(double span, int n) {
+__host__ __device__ __forceinline__ double halfwidth_real(double span, int n) {
 #pragma clang fp contract(off)
     return 0.5 * span * (double)n + 0.5;
 }
 
-__device__ __forceinline__ double listing_vsmlsq(double scale) {
+__host__ __device__ __forceinline__ double listing_vsmlsq(double scale) {
 #pragma clang fp contract(off)
     return 1.0e-6 * scale * scale;
 }
 
-// Size classes: one wavefront per trial, PPL points per lane.
-constexpr int kClassPPL[] = {1, 2, 3, 4, 6, 8};
-constexpr int kNumClasses = 6;
-constexpr int kMaxSingleWave = 64 * 8;
+// Trial-group shapes (NW wavefronts, PPL points per thread): a light curve of
+// n points runs on any shape with 64*NW*PPL >= n.
+#define SSG_SHAPES(X) \
+    X(1, 1) X(1, 2) X(2, 1) X(1, 3) X(1, 4) X(2, 2) X(4, 1) X(2, 3) X(4, 2) X(4, 4) X(8, 2) \
+    X(8, 4) X(16, 3) X(16, 4)
+constexpr int shape_id(int nw, int ppl) { return nw * 16 + ppl; }
+struct ShapeInfo {
+    int nw, ppl;
+};
+constexpr ShapeInfo kShapes[] = {
+#define SSG_SHAPE_INFO(nw, ppl) {nw, ppl},
+    SSG_SHAPES(SSG_SHAPE_INFO)
+#undef SSG_SHAPE_INFO
+};
+constexpr int kNumShapes = (int)(sizeof(kShapes) / sizeof(kShapes[0]));
 
-int class_of_length(int64_t n);  // index into kClassPPL, -1 if too long
+int trial_lds_bytes(int nw, int ppl, int ext);   // dynamic LDS of one trial group
+int trial_halfwidth(int n, double span);         // window half-width b(n, span)
 
+// Shape selection on the device: the first rule with n <= n_max, else the
+// first default entry with n <= n_max.  Objects longer than max_points or
+// whose shape is not runnable (LDS) get status SS_OBJ_TOO_LONG and go to
+// class `fallback`.
+struct ShapeRules {
+    int32_t n_rules, n_def, max_points, fallback;
+    int32_t rule_n[16], rule_shape[16];
+    int32_t def_n[16], def_shape[16];
+    uint32_t runnable;  // bit per shape index
+};
+
+// Zeroes the per-class object counts and queue heads (a kernel, so that the
+// sequence stays valid inside a captured graph).
+hipError_t launch_reset(int32_t *counts, unsigned long long *queues, int n, hipStream_t stream);
+
+// Prep plus planning: status, tt/w/yc, chi0, and the object's entry in its
+// shape class (objs[class * n_obj + slot], counts[class]).
 hipError_t launch_prep(const int64_t *offsets, const double *t, const double *y, const double *e,
-                       int64_t n_obj, double *tt, double *w, double *yc, float *w32, float *yc32,
-                       double *chi0, int32_t *status, hipStream_t stream);
+                       int64_t n_obj, int64_t n_points, double *tt, double *w, double *yc, float *w32, float *yc32,
+                       double *chi0, int32_t *status, const ShapeRules &rules, int32_t *objs,
+                       int32_t *counts, hipStream_t stream);
 
-hipError_t launch_trials(int cls, int precision, const TrialLaunch &L, hipStream_t stream);
+// Persistent launch of one class: grid = co-resident workgroups (at most
+// max_items).
+hipError_t launch_trials(int shape_id, int precision, const TrialLaunch &L, int64_t max_items,
+                         int n_cu, hipStream_t stream);
 
 hipError_t launch_finalize(const double *part_p, const int32_t *part_k, int64_t n_obj,
                            int32_t n_tiles, const int32_t *status, double fmin, double df,

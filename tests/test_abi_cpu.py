@@ -42,7 +42,7 @@ def test_null_arguments_rejected_without_device():
     g = ssg._Grid(0.1, 10.0, 100)
     p = ssg._Params()
     lib.ss_params_default(ctypes.byref(p))
-    c = ssg._Catalog(1, None, None, None, None)
+    c = ssg._Catalog(1, 10, None, None, None, None)
     rc = lib.ss_periodogram(None, ctypes.byref(c), ctypes.byref(g), ctypes.byref(p), None, None,
                             None)
     assert rc == ssg.SS_ERR_INVALID_ARG

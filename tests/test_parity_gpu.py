@@ -172,3 +172,68 @@ def test_best_period_matches_periodogram(ctx, method):
         assert bw.cpu().numpy()[o] == pg[o, k]
         f = oracle.freq(grid[0], grid[1], grid[2], k)
         assert bp.cpu().numpy()[o] == 1.0 / f
+
+
+@pytest.mark.parametrize("method", [oracle.SS, oracle.SSSP])
+def test_every_shape_gives_the_oracle_result(ctx, method):
+    # the same light curves forced through every trial-group shape that holds
+    # them: identical to the oracle within tolerance, and to each other
+    import torch
+    lens = [150, 200, 250]
+    cats = [synth.make_catalog(300 + i, 1, n, 800.0, (0.3, 5.0), 0.05, shapes=(i % 3,))
+            for i, n in enumerate(lens)]
+    offs = np.concatenate([[0], np.cumsum([c.offsets[-1] for c in cats])]).astype(np.int64)
+    t = np.concatenate([c.t for c in cats])
+    y = np.concatenate([c.y for c in cats])
+    e = np.concatenate([c.e for c in cats])
+    grid = (0.2, 4.0, 37)
+    po, _ = oracle.periodogram(method, offs, t, y, e, *grid)
+    ref = None
+    try:
+        for nw, ppl in ssg.shapes():
+            if 64 * nw * ppl < 250:
+                continue
+            ctx.set_shape(0, 0, 0)
+            ctx.set_shape(250, nw, ppl)
+            pg, st = _gpu_pgram(ctx, method, offs, t, y, e, grid)
+            if (st == ssg.OBJ_TOO_LONG).all():  # shape does not fit the LDS at span 0.5
+                continue
+            _assert_pgram_close(pg, po, what=f"shape {nw}x{ppl}")
+            if ref is None:
+                ref = pg
+            np.testing.assert_allclose(pg, ref, rtol=0, atol=1e-11)
+    finally:
+        ctx.set_shape(0, 0, 0)
+
+
+@pytest.mark.parametrize("method", [oracle.SS, oracle.SSSP])
+def test_long_light_curves(ctx, method):
+    # multi-wave trial groups: lengths across the 512/1024/2048/3072 shapes,
+    # including the dense 3,000-point eclipsing binary
+    cats = [synth.make_catalog(500 + i, 1, n, 3000.0, (0.2, 10.0), 0.02, shapes=(2,))
+            for i, n in enumerate([600, 1024, 1025, 2049, 3000])]
+    offs = np.concatenate([[0], np.cumsum([c.offsets[-1] for c in cats])]).astype(np.int64)
+    t = np.concatenate([c.t for c in cats])
+    y = np.concatenate([c.y for c in cats])
+    e = np.concatenate([c.e for c in cats])
+    grid = (0.01, 20.0, 23)
+    po, so = oracle.periodogram(method, offs, t, y, e, *grid)
+    pg, sg = _gpu_pgram(ctx, method, offs, t, y, e, grid)
+    assert np.array_equal(so, sg)
+    _assert_pgram_close(pg, po, what="long light curves")
+    pg32, _ = _gpu_pgram(ctx, method, offs, t, y, e, grid, ssg.Params(precision=ssg.SS_FP32C))
+    rel = np.abs(pg32 - po) / np.maximum(1 - po, 1e-12)
+    assert np.mean(rel > 1e-4) <= 0.05 and rel.max() <= 1e-2, rel.max()
+
+
+def test_tile_size_does_not_change_results(ctx):
+    cat, _ = synth.catalog_uneven(seed=44, n_obj=5)
+    grid = (0.1, 10.0, 211)
+    pg0, _ = _gpu_pgram(ctx, oracle.SS, cat.offsets, cat.t, cat.y, cat.e, grid)
+    try:
+        for tile in (1, 7, 64, 500):
+            ctx.set_tile(tile)
+            pg, _ = _gpu_pgram(ctx, oracle.SS, cat.offsets, cat.t, cat.y, cat.e, grid)
+            np.testing.assert_array_equal(pg, pg0)
+    finally:
+        ctx.set_tile(0)
