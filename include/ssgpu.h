@@ -162,6 +162,80 @@ int ss_ctx_set_tile(ss_ctx *ctx, int32_t tile_f);
 int ss_ctx_set_timing(ss_ctx *ctx, int enable);
 int ss_ctx_trial_kernel_ms(ss_ctx *ctx, double *ms, int32_t *n_launches);
 
+/* ---- learned frequency proposal + exact refine (search-and-refine, Sec. 6)
+ *
+ * A set encoder ranks 1024 log-spaced frequency bins of the search grid for
+ * each object; the exact Super Smoother (or SSSP) trial kernel then searches
+ * only the fine-grid frequencies inside the top bins.  The full-grid search
+ * (ss_best_period) stays the reference: a refined result is the full-grid
+ * result whenever the full-grid best frequency lies in the refined set.
+ *
+ * Bins: bin b holds the grid indices k with E_b <= f_k < E_{b+1}, where
+ * E_b = f_min * (f_max / f_min)^(b / 1024) in FP64 (b = 0..1024), f_k as in
+ * ss_grid.  ss_bin_table writes the first index of each bin (and n_freq as
+ * entry 1024) to a HOST array of 1025 int64; it needs no device.
+ *
+ * Network (SS_ENC_PARAMS FP32 parameters, flat, row-major, input dimension
+ * first): W1[80][64], W2[64][128], b2[128], W3[128][1024], b3[1024].
+ * Per point i of an object: features x_i[80] = sin and cos of 2 pi g_m tt_i
+ * (slots 2m, 2m+1; g_m = 32 frequencies log-spaced over [f_min, f_max], ends
+ * included), (y_i - ybar)/sigma (slot 64), e_i/sigma (slot 65) and 1 (slot
+ * 66; row 66 of W1 is the first layer's bias), other slots 0; ybar is the
+ * e^-2-weighted mean, sigma^2 = chi0 / sum(e^-2), tt = t - min t.  Then
+ * h1 = relu(x W1), h2 = relu(h1 W2 + b2), emb = mean over points of h2,
+ * logits = emb W3 + b3.  The per-point layers run in BF16 on the matrix
+ * cores with FP32 accumulation; the head, the loss and Adam run in FP32.
+ * Objects with a nonzero status get emb = 0 (logits = b3) and no refine.
+ */
+#define SS_ENC_PARAMS 145536
+#define SS_ENC_BINS 1024
+
+/* First grid index of each log bin (host output, 1025 entries). */
+int ss_bin_table(const ss_grid *grid, int64_t *first_k);
+
+/* Number of encoder parameters (SS_ENC_PARAMS). */
+int ss_enc_num_params(void);
+
+/* Encoder forward: emb [n_obj][128] and logits [n_obj][1024] (device FP32),
+ * feature frequencies and bins from `grid`; obj_status as in ss_best_period. */
+int ss_enc_forward(ss_ctx *ctx, const ss_catalog *cat, const ss_grid *grid,
+                   const float *enc_params, float *emb, float *logits, int32_t *obj_status,
+                   void *stream);
+
+/* Training gradient: mean softmax cross-entropy of the logits against
+ * labels[n_obj] (bin indices; objects with a label outside [0, 1024) or a
+ * nonzero status contribute 0 but still count in the mean), written to
+ * *loss (device float), and its gradient with respect to every parameter
+ * (grad: device, SS_ENC_PARAMS floats, overwritten).  Deterministic for a
+ * given device and catalog.  Needs n_obj >= 1. */
+int ss_enc_train_grad(ss_ctx *ctx, const ss_catalog *cat, const ss_grid *grid,
+                      const float *enc_params, const int32_t *labels, float *grad, float *loss,
+                      int32_t *obj_status, void *stream);
+
+/* One Adam step on FP32 master weights, in place: m = b1 m + (1-b1) g,
+ * v = b2 v + (1-b2) g^2, p -= lr (m / (1-b1^step)) / (sqrt(v / (1-b2^step)) + eps).
+ * step counts from 1.  All arrays are device, n floats. */
+int ss_adam_step(float *params, const float *grad, float *m, float *v, int64_t n, int32_t step,
+                 float lr, float beta1, float beta2, float eps, void *stream);
+
+/* Refine from given logits [n_obj][1024] (device FP32): per object the top_k
+ * bins by logit (NaN ranks lowest; equal logits: lower bin first), each
+ * widened by `margin` bins on both sides, are searched at every grid
+ * frequency they hold, and the best over that set is reported exactly as
+ * ss_best_period reports it (lowest index among equal powers).  1 <= top_k
+ * <= 1024, 0 <= margin <= 64. */
+int ss_refine_best_period(ss_ctx *ctx, int32_t method, const ss_catalog *cat,
+                          const ss_grid *grid, const ss_params *params, const float *logits,
+                          int32_t top_k, int32_t margin, int64_t *best_idx, double *best_period,
+                          double *best_power, int32_t *obj_status, void *stream);
+
+/* Encoder forward + refine in one call.  The first call on a new grid uploads
+ * the bin table synchronously. */
+int ss_learned_best_period(ss_ctx *ctx, int32_t method, const ss_catalog *cat,
+                           const ss_grid *grid, const ss_params *params, const float *enc_params,
+                           int32_t top_k, int32_t margin, int64_t *best_idx, double *best_period,
+                           double *best_power, int32_t *obj_status, void *stream);
+
 /* Message for the last failing call on this host thread ("" if none). */
 const char *ss_last_error(void);
 

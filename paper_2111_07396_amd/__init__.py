@@ -28,7 +28,11 @@ MAX_POINTS = 4096
 EXPORTED = ("ss_params_default", "ss_ctx_create", "ss_ctx_destroy", "ss_periodogram",
             "sssp_periodogram", "ss_best_period", "ss_num_shapes", "ss_shape_info",
             "ss_ctx_set_shape", "ss_ctx_set_tile", "ss_ctx_set_timing", "ss_ctx_trial_kernel_ms",
-            "ss_last_error", "ss_version")
+            "ss_last_error", "ss_version", "ss_bin_table", "ss_enc_num_params", "ss_enc_forward",
+            "ss_enc_train_grad", "ss_adam_step", "ss_refine_best_period",
+            "ss_learned_best_period")
+ENC_PARAMS = 145536
+ENC_BINS = 1024
 
 
 def shapes():
@@ -109,6 +113,24 @@ def load_library(path: str = LIB_PATH):
     lib.ss_last_error.restype = ctypes.c_char_p
     lib.ss_version.argtypes = []
     lib.ss_version.restype = ctypes.c_int
+    lib.ss_bin_table.argtypes = [ctypes.POINTER(_Grid), vp]
+    lib.ss_bin_table.restype = ctypes.c_int
+    lib.ss_enc_num_params.argtypes = []
+    lib.ss_enc_num_params.restype = ctypes.c_int
+    lib.ss_enc_forward.argtypes = [vp, ctypes.POINTER(_Catalog), ctypes.POINTER(_Grid), vp, vp,
+                                   vp, vp, vp]
+    lib.ss_enc_forward.restype = ctypes.c_int
+    lib.ss_enc_train_grad.argtypes = [vp, ctypes.POINTER(_Catalog), ctypes.POINTER(_Grid), vp,
+                                      vp, vp, vp, vp, vp]
+    lib.ss_enc_train_grad.restype = ctypes.c_int
+    lib.ss_adam_step.argtypes = [vp, vp, vp, vp, i64, i32, ctypes.c_float, ctypes.c_float,
+                                 ctypes.c_float, ctypes.c_float, vp]
+    lib.ss_adam_step.restype = ctypes.c_int
+    for name in ("ss_refine_best_period", "ss_learned_best_period"):
+        f = getattr(lib, name)
+        f.argtypes = [vp, i32, ctypes.POINTER(_Catalog), ctypes.POINTER(_Grid),
+                      ctypes.POINTER(_Params), vp, i32, i32, vp, vp, vp, vp, vp]
+        f.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -162,6 +184,36 @@ class DeviceCatalog:
             raise ValueError("t, y and e must have the same length")
         return _Catalog(self.n_obj, self.t.numel(), self.offsets.data_ptr(), self.t.data_ptr(),
                         self.y.data_ptr(), self.e.data_ptr())
+
+
+def bin_table(grid):
+    """First grid index of each of the 1024 log bins, plus n_freq (host int64[1025])."""
+    import numpy as np
+    lib = load_library()
+    out = np.zeros(ENC_BINS + 1, dtype=np.int64)
+    g = _Grid(float(grid[0]), float(grid[1]), int(grid[2]))
+    _check(lib.ss_bin_table(ctypes.byref(g), ctypes.c_void_p(out.ctypes.data)))
+    return out
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _f32_dev(t, n, what):
+    if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous() or t.numel() != n:
+        raise ValueError(f"{what} must be a contiguous CUDA float32 tensor of {n} elements")
+
+
+def adam_step(params, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    """One in-place Adam step on FP32 device tensors (step counts from 1)."""
+    n = params.numel()
+    for t, w in ((params, "params"), (grad, "grad"), (m, "m"), (v, "v")):
+        _f32_dev(t, n, w)
+    load_library()
+    _check(_lib.ss_adam_step(_ptr(params), _ptr(grad), _ptr(m), _ptr(v), n, int(step),
+                             float(lr), float(beta1), float(beta2), float(eps),
+                             _stream_ptr(stream)))
 
 
 def _stream_ptr(stream):
@@ -254,4 +306,78 @@ class Context:
                                    ctypes.byref(p), ctypes.c_void_p(bi.data_ptr()),
                                    ctypes.c_void_p(bp.data_ptr()), ctypes.c_void_p(bw.data_ptr()),
                                    ctypes.c_void_p(st.data_ptr()), _stream_ptr(stream)))
+        return bi, bp, bw, st
+
+    def _best_out(self, n_obj, dev, out):
+        if out is None:
+            out = (torch.empty(n_obj, dtype=torch.int64, device=dev),
+                   torch.empty(n_obj, dtype=torch.float64, device=dev),
+                   torch.empty(n_obj, dtype=torch.float64, device=dev),
+                   torch.empty(n_obj, dtype=torch.int32, device=dev))
+        return out
+
+    def enc_forward(self, cat, grid, enc_params, stream=None):
+        """(emb [n_obj,128], logits [n_obj,1024], status) of the set encoder."""
+        n_obj = cat.n_obj
+        dev = cat.offsets.device
+        _f32_dev(enc_params, ENC_PARAMS, "enc_params")
+        emb = torch.empty((n_obj, 128), dtype=torch.float32, device=dev)
+        logits = torch.empty((n_obj, ENC_BINS), dtype=torch.float32, device=dev)
+        st = torch.empty(n_obj, dtype=torch.int32, device=dev)
+        g = _Grid(float(grid[0]), float(grid[1]), int(grid[2]))
+        c = cat._c()
+        _check(_lib.ss_enc_forward(self._h, ctypes.byref(c), ctypes.byref(g), _ptr(enc_params),
+                                   _ptr(emb), _ptr(logits), _ptr(st), _stream_ptr(stream)))
+        return emb, logits, st
+
+    def enc_train_grad(self, cat, grid, enc_params, labels, grad=None, loss=None, stream=None):
+        """(grad [ENC_PARAMS], loss [1], status) of the mean cross-entropy."""
+        n_obj = cat.n_obj
+        dev = cat.offsets.device
+        _f32_dev(enc_params, ENC_PARAMS, "enc_params")
+        if labels.dtype != torch.int32 or not labels.is_cuda or labels.numel() != n_obj:
+            raise ValueError("labels must be a CUDA int32 tensor of n_obj elements")
+        labels = labels.contiguous()
+        if grad is None:
+            grad = torch.empty(ENC_PARAMS, dtype=torch.float32, device=dev)
+        if loss is None:
+            loss = torch.empty(1, dtype=torch.float32, device=dev)
+        st = torch.empty(n_obj, dtype=torch.int32, device=dev)
+        g = _Grid(float(grid[0]), float(grid[1]), int(grid[2]))
+        c = cat._c()
+        _check(_lib.ss_enc_train_grad(self._h, ctypes.byref(c), ctypes.byref(g),
+                                      _ptr(enc_params), _ptr(labels), _ptr(grad), _ptr(loss),
+                                      _ptr(st), _stream_ptr(stream)))
+        return grad, loss, st
+
+    def refine_best_period(self, method, cat, grid, logits, top_k=16, margin=1, params=None,
+                           out=None, stream=None):
+        """Exact search over the fine-grid frequencies of each object's top bins."""
+        params = params or Params()
+        n_obj = cat.n_obj
+        _f32_dev(logits, n_obj * ENC_BINS, "logits")
+        bi, bp, bw, st = self._best_out(n_obj, cat.offsets.device, out)
+        g = _Grid(float(grid[0]), float(grid[1]), int(grid[2]))
+        c = cat._c()
+        p = params._c()
+        _check(_lib.ss_refine_best_period(self._h, int(method), ctypes.byref(c), ctypes.byref(g),
+                                          ctypes.byref(p), _ptr(logits), int(top_k), int(margin),
+                                          _ptr(bi), _ptr(bp), _ptr(bw), _ptr(st),
+                                          _stream_ptr(stream)))
+        return bi, bp, bw, st
+
+    def learned_best_period(self, method, cat, grid, enc_params, top_k=16, margin=1, params=None,
+                            out=None, stream=None):
+        """Encoder proposal + exact refine in one call."""
+        params = params or Params()
+        n_obj = cat.n_obj
+        _f32_dev(enc_params, ENC_PARAMS, "enc_params")
+        bi, bp, bw, st = self._best_out(n_obj, cat.offsets.device, out)
+        g = _Grid(float(grid[0]), float(grid[1]), int(grid[2]))
+        c = cat._c()
+        p = params._c()
+        _check(_lib.ss_learned_best_period(self._h, int(method), ctypes.byref(c),
+                                           ctypes.byref(g), ctypes.byref(p), _ptr(enc_params),
+                                           int(top_k), int(margin), _ptr(bi), _ptr(bp), _ptr(bw),
+                                           _ptr(st), _stream_ptr(stream)))
         return bi, bp, bw, st

@@ -32,14 +32,14 @@ __global__ __launch_bounds__(kWave *kPrepWaves) void prep_kernel(
     const double *__restrict__ y, const double *__restrict__ e, int64_t n_obj, int64_t n_points,
     double *__restrict__ tt, double *__restrict__ w, double *__restrict__ yc,
     float *__restrict__ w32, float *__restrict__ yc32, double *__restrict__ chi0,
-    int32_t *__restrict__ status, ShapeRules rules, int32_t *__restrict__ objs,
+    double *__restrict__ sw_out, int32_t *__restrict__ status, ShapeRules rules, int32_t *__restrict__ objs,
     int32_t *__restrict__ counts) {
     const int lane = threadIdx.x % kWave;
     const int64_t obj = (int64_t)blockIdx.x * kPrepWaves + threadIdx.x / kWave;
     if (obj >= n_obj) return;
     const int64_t a = offsets[obj], n = offsets[obj + 1] - a;
     int32_t st = 0;
-    double c0 = __builtin_nan("");
+    double c0 = __builtin_nan(""), swt = __builtin_nan("");
     if (a < 0 || n < 0 || a + n > n_points) {
         st = 6;
     } else if (n < 5) {
@@ -63,6 +63,7 @@ __global__ __launch_bounds__(kWave *kPrepWaves) void prep_kernel(
             tmin = wave_min(tmin);
             sw = wave_sum(sw);
             swy = wave_sum(swy);
+            swt = sw;
             const double ybar = swy / sw;
             double acc = 0.0;
             for (int64_t i = lane; i < n; i += kWave) {
@@ -88,6 +89,7 @@ __global__ __launch_bounds__(kWave *kPrepWaves) void prep_kernel(
         }
         status[obj] = st;
         chi0[obj] = c0;
+        if (sw_out) sw_out[obj] = swt;
         const int32_t slot = atomicAdd(&counts[cls], 1);
         objs[(int64_t)cls * n_obj + slot] = (int32_t)obj;
     }
@@ -137,14 +139,13 @@ hipError_t launch_reset(int32_t *counts, unsigned long long *queues, int n, hipS
 
 hipError_t launch_prep(const int64_t *offsets, const double *t, const double *y, const double *e,
                        int64_t n_obj, int64_t n_points, double *tt, double *w, double *yc, float *w32, float *yc32,
-                       double *chi0, int32_t *status, const ShapeRules &rules, int32_t *objs,
-                       int32_t *counts, hipStream_t stream) {
+                       double *chi0, double *sw, int32_t *status, const ShapeRules &rules,
+                       int32_t *objs, int32_t *counts, hipStream_t stream) {
     if (n_obj <= 0) return hipSuccess;
     const int64_t blocks = (n_obj + kPrepWaves - 1) / kPrepWaves;
     hipLaunchKernelGGL(prep_kernel, dim3((unsigned)blocks), dim3(kWave * kPrepWaves), 0, stream,
-                       offsets, t, y, e, n_obj, n_points, tt, w, yc, w32, yc32, chi0, status, rules,
-                       objs,
-                       counts);
+                       offsets, t, y, e, n_obj, n_points, tt, w, yc, w32, yc32, chi0, sw, status,
+                       rules, objs, counts);
     return hipGetLastError();
 }
 

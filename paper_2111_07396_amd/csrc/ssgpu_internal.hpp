@@ -38,6 +38,8 @@ struct TrialLaunch {
     float *pgram32;       // [n_obj * n_freq] or null
     double *part_p;       // [n_obj * n_tiles] or null
     int32_t *part_k;      // [n_obj * n_tiles] or null
+    const int64_t *ranges;  // refine: [n_obj][n_tiles] of (k_begin, k_end), or null for
+                            // the full grid cut into tiles of tile_f
 };
 
 // Expressions that must round exactly like their plain C statement (no
@@ -98,8 +100,8 @@ hipError_t launch_reset(int32_t *counts, unsigned long long *queues, int n, hipS
 // shape class (objs[class * n_obj + slot], counts[class]).
 hipError_t launch_prep(const int64_t *offsets, const double *t, const double *y, const double *e,
                        int64_t n_obj, int64_t n_points, double *tt, double *w, double *yc, float *w32, float *yc32,
-                       double *chi0, int32_t *status, const ShapeRules &rules, int32_t *objs,
-                       int32_t *counts, hipStream_t stream);
+                       double *chi0, double *sw, int32_t *status, const ShapeRules &rules,
+                       int32_t *objs, int32_t *counts, hipStream_t stream);
 
 // Persistent launch of one class: grid = co-resident workgroups (at most
 // max_items).
@@ -110,5 +112,40 @@ hipError_t launch_finalize(const double *part_p, const int32_t *part_k, int64_t 
                            int32_t n_tiles, const int32_t *status, double fmin, double df,
                            int64_t *best_idx, double *best_period, double *best_power,
                            hipStream_t stream);
+
+// ---- learned frequency proposal (set encoder) ----
+constexpr int kEncK1 = 80, kEncH1 = 64, kEncH2 = 128, kEncBins = 1024, kEncNFreq = 32;
+constexpr int kEncParams =
+    kEncK1 * kEncH1 + kEncH1 * kEncH2 + kEncH2 + kEncH2 * kEncBins + kEncBins;
+
+struct EncArgs {
+    int n_obj;
+    const int64_t *offsets;
+    const double *tt, *yc, *e, *chi0, *sw;  // prepped catalog (tt, yc, chi0, sw) and raw e
+    const int32_t *status;
+    const float *params;     // FP32 master parameters
+    double g[kEncNFreq];     // feature frequencies
+    float *emb, *act;        // [n_obj][128]; act may be null
+    const float *dE;         // backward: dL/d emb [n_obj][128]
+    float *partial;          // backward: per-wave W1/W2 gradient slots
+};
+
+int enc_fwd_lds_bytes();
+int enc_bwd_lds_bytes(int waves);
+int enc_mlp_grad_floats();
+int enc_bwd_waves(int n_obj, int n_cu);
+hipError_t launch_enc_fwd(const EncArgs &A, int n_cu, hipStream_t s);
+hipError_t launch_head_fwd(const float *emb, const float *prm, int n_obj, float *logits,
+                           hipStream_t s);
+// Cross-entropy, head gradients, per-point backward and the gradient
+// reduction (grad must hold kEncParams floats; every entry is written).
+hipError_t launch_train_tail(const EncArgs &A, const float *logits, const int32_t *labels,
+                             float *dlog, float *loss_o, float *dE, float *grad, float *loss,
+                             int n_waves, hipStream_t s);
+hipError_t launch_adam(float *p, const float *g, float *m, float *v, int64_t n, float lr,
+                       float b1, float b2, float eps, float c1, float c2, hipStream_t s);
+hipError_t launch_plan(const float *logits, const int32_t *status, const int64_t *bin_k,
+                       int n_obj, int top_k, int margin, int chunk, int n_rng, int64_t *ranges,
+                       hipStream_t s);
 
 }  // namespace ssg

@@ -764,7 +764,8 @@ __device__ double run_trial(Group<P, NW, PPL> &G, unsigned char *lds, const Layo
     return 1.0 - chi2 / chi0;
 }
 
-// One work item: an object and a tile of consecutive trial frequencies.
+// One work item: an object and a run of consecutive trial frequencies (a tile
+// of the full grid, or one refine range).
 template <class P, int NW, int PPL, int METHOD>
 __device__ void run_item(Group<P, NW, PPL> &G, unsigned char *lds, const Layout &Y,
                          const TrialLaunch &L, int64_t item) {
@@ -772,9 +773,15 @@ __device__ void run_item(Group<P, NW, PPL> &G, unsigned char *lds, const Layout 
     const int64_t ci = item / L.n_tiles;
     const int32_t tile = (int32_t)(item - ci * L.n_tiles);
     const int obj = L.objs[ci];
-    const int64_t k0 = (int64_t)tile * L.tile_f;
-    const int64_t k1 = (k0 + L.tile_f < L.n_freq) ? k0 + L.tile_f : L.n_freq;
     const int64_t part = (int64_t)obj * L.n_tiles + tile;
+    int64_t k0, k1;
+    if (L.ranges) {
+        k0 = L.ranges[2 * part];
+        k1 = L.ranges[2 * part + 1];
+    } else {
+        k0 = (int64_t)tile * L.tile_f;
+        k1 = (k0 + L.tile_f < L.n_freq) ? k0 + L.tile_f : L.n_freq;
+    }
     const int64_t row = (int64_t)obj * L.n_freq;
 
     if (L.cat.status[obj] != 0) {

@@ -1,0 +1,141 @@
+"""Training and evaluation of the learned frequency proposal.
+
+Labels are the bin of the full-grid Super Smoother best frequency computed by
+the library itself (`ss_best_period`); training runs the library's own
+encoder gradient and Adam kernels (`ss_enc_train_grad`, `ss_adam_step`) on
+device-resident mini-batches.  Evaluation compares the search-and-refine
+result (`ss_learned_best_period`) with the full-grid result on the same
+objects: agreement is the fraction of objects whose refined best index equals
+the full-grid best index, and the speed-up is the ratio of the two calls'
+wall times on the same GPU.
+
+Everything here is orchestration: array marshalling, batching and timing.
+"""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+import torch
+
+from . import (DeviceCatalog, ENC_BINS, ENC_PARAMS, SS_FP64, SS_METHOD_SS, Params, adam_step,
+               bin_table)
+
+
+def init_params(seed: int = 0) -> np.ndarray:
+    """He-style initialisation: zero biases, zero weight rows for the unused
+    feature slots 67..79 (row 66 of W1 is the first layer's bias)."""
+    rng = np.random.default_rng(seed)
+    w1 = rng.normal(0, np.sqrt(2.0 / 66), (80, 64))
+    w1[66:] = 0.0
+    w2 = rng.normal(0, np.sqrt(2.0 / 64), (64, 128))
+    w3 = rng.normal(0, np.sqrt(1.0 / 128), (128, ENC_BINS))
+    out = np.concatenate([w1.ravel(), w2.ravel(), np.zeros(128), w3.ravel(), np.zeros(ENC_BINS)])
+    assert out.size == ENC_PARAMS
+    return out
+
+
+def view(dc: DeviceCatalog, lo: int, hi: int) -> DeviceCatalog:
+    """Objects [lo, hi) of a device catalog, without copying."""
+    return DeviceCatalog(dc.offsets[lo:hi + 1], dc.t, dc.y, dc.e)
+
+
+def full_grid_best(ctx, dc: DeviceCatalog, grid, method=SS_METHOD_SS, precision=SS_FP64,
+                   chunk: int = 20000):
+    """(best_idx int64, best_power f64, status int32) on the host, computed in
+    object chunks."""
+    n = dc.n_obj
+    bi = np.empty(n, dtype=np.int64)
+    bw = np.empty(n, dtype=np.float64)
+    st = np.empty(n, dtype=np.int32)
+    for lo in range(0, n, chunk):
+        hi = min(n, lo + chunk)
+        r = ctx.ss_best_period(method, view(dc, lo, hi), grid, Params(precision=precision))
+        bi[lo:hi] = r[0].cpu().numpy()
+        bw[lo:hi] = r[2].cpu().numpy()
+        st[lo:hi] = r[3].cpu().numpy()
+    return bi, bw, st
+
+
+def labels_from_best(best_idx: np.ndarray, grid) -> np.ndarray:
+    """Bin of each best index (-1 where there is none)."""
+    tab = bin_table(grid)
+    lab = np.searchsorted(tab, best_idx, side="right") - 1
+    return np.where(best_idx >= 0, lab, -1).astype(np.int32)
+
+
+def train(ctx, dc: DeviceCatalog, labels: np.ndarray, grid, epochs: int = 10, batch: int = 512,
+          lr: float = 2e-3, seed: int = 0, params: np.ndarray | None = None, log=None):
+    """Adam on mean cross-entropy over fixed contiguous batches in a shuffled
+    order each epoch.  Returns (params tensor, per-epoch mean losses)."""
+    dev = dc.offsets.device
+    p = torch.tensor(init_params(seed) if params is None else params, dtype=torch.float32,
+                     device=dev)
+    m = torch.zeros_like(p)
+    v = torch.zeros_like(p)
+    g = torch.empty_like(p)
+    loss = torch.empty(1, dtype=torch.float32, device=dev)
+    lab = torch.tensor(labels, dtype=torch.int32, device=dev)
+    n = dc.n_obj
+    starts = np.arange(0, n, batch)
+    rng = np.random.default_rng(seed)
+    step = 0
+    history = []
+    for ep in range(epochs):
+        tot = torch.zeros((), dtype=torch.float64, device=dev)
+        for lo in rng.permutation(starts):
+            hi = min(n, lo + batch)
+            ctx.enc_train_grad(view(dc, lo, hi), grid, p, lab[lo:hi], grad=g, loss=loss)
+            step += 1
+            adam_step(p, g, m, v, step, lr)
+            tot += loss[0].double() * (hi - lo)
+        history.append(float(tot.item()) / n)
+        if log:
+            log(f"epoch {ep + 1}/{epochs}: loss {history[-1]:.4f}")
+    return p, history
+
+
+def topk_recall(ctx, dc: DeviceCatalog, grid, params, labels: np.ndarray, top_k: int = 16,
+                margin: int = 1, chunk: int = 20000) -> float:
+    """Fraction of labelled objects whose label bin lies in the widened top-k."""
+    hits, tot = 0, 0
+    for lo in range(0, dc.n_obj, chunk):
+        hi = min(dc.n_obj, lo + chunk)
+        _, logits, st = ctx.enc_forward(view(dc, lo, hi), grid, params)
+        top = torch.topk(logits, top_k, dim=1).indices.cpu().numpy()
+        lab = labels[lo:hi]
+        ok = (lab >= 0) & (st.cpu().numpy() == 0)
+        d = np.abs(top - lab[:, None]).min(axis=1)
+        hits += int(((d <= margin) & ok).sum())
+        tot += int(ok.sum())
+    return hits / max(tot, 1)
+
+
+def compare(ctx, dc: DeviceCatalog, grid, params, top_k=16, margin=1, method=SS_METHOD_SS,
+            precision=SS_FP64, repeats: int = 2):
+    """Agreement and wall times of learned+refine against the full grid."""
+    prm = Params(precision=precision)
+    full = ctx.ss_best_period(method, dc, grid, prm)
+    lrn = ctx.learned_best_period(method, dc, grid, params, top_k, margin, prm)
+    torch.cuda.synchronize()
+
+    def timed(fn):
+        best = None
+        for _ in range(repeats):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            best = dt if best is None else min(best, dt)
+        return best
+
+    t_full = timed(lambda: ctx.ss_best_period(method, dc, grid, prm, out=full))
+    t_lrn = timed(lambda: ctx.learned_best_period(method, dc, grid, params, top_k, margin, prm,
+                                                  out=lrn))
+    fi, li = full[0].cpu().numpy(), lrn[0].cpu().numpy()
+    ok = (full[3].cpu().numpy() == 0) & (fi >= 0)
+    agree = float(np.mean(fi[ok] == li[ok])) if ok.any() else float("nan")
+    return {"agreement": agree, "objects": int(ok.sum()), "t_full_s": t_full,
+            "t_learned_s": t_lrn, "speedup": t_full / t_lrn,
+            "full_obj_per_s": dc.n_obj / t_full, "learned_obj_per_s": dc.n_obj / t_lrn}

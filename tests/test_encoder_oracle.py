@@ -1,0 +1,174 @@
+"""Pins of the FP64 reference of the learned frequency proposal (CPU only).
+
+The analytic gradient is checked against central finite differences, the
+forward pass against an independent per-point loop, the features against
+their closed forms (unit-norm sin/cos pairs, standardised magnitudes), and
+the Adam step against its first-step closed form (|update| = lr)."""
+import numpy as np
+import pytest
+
+from oracle import encoder as enc
+from paper_2111_07396_amd import synth
+
+
+def _batch(n_obj=3, seed=5):
+    cat = synth.make_catalog(seed, n_obj, 40, 100.0, (0.3, 5.0), 0.05)
+    feats = []
+    for o in range(n_obj):
+        a, b = cat.offsets[o], cat.offsets[o + 1]
+        feats.append(enc.features(cat.t[a:b], cat.y[a:b], cat.e[a:b], 0.1, 10.0))
+    labels = np.array([3, 500, 1023])[:n_obj]
+    return feats, labels
+
+
+def test_features_closed_forms():
+    feats, _ = _batch()
+    x = feats[0]
+    assert x.shape == (40, enc.K1)
+    s, c = x[:, 0:64:2], x[:, 1:64:2]
+    np.testing.assert_allclose(s * s + c * c, 1.0, atol=1e-12)
+    # the earliest point has tt = 0: phase 0 at every feature frequency
+    i0 = np.argmin(np.abs(x[:, 1:64:2] - 1.0).sum(axis=1))
+    np.testing.assert_allclose(x[i0, 0:64:2], 0.0, atol=1e-12)
+    assert np.all(x[:, enc.ONE_SLOT] == 1.0) and np.all(x[:, enc.ONE_SLOT + 1:] == 0.0)
+
+
+def test_features_standardised():
+    rng = np.random.default_rng(0)
+    t = np.sort(rng.uniform(0, 50, 64))
+    y = rng.normal(12.0, 0.3, 64)
+    e = np.full(64, 0.02)
+    x = enc.features(t, y, e, 0.1, 10.0)
+    # equal errors: weighted mean/deviation are the plain population ones
+    np.testing.assert_allclose(x[:, 64].mean(), 0.0, atol=1e-12)
+    np.testing.assert_allclose(np.sqrt((x[:, 64] ** 2).mean()), 1.0, atol=1e-12)
+    np.testing.assert_allclose(x[:, 65], 0.02 / y.std(), rtol=1e-12)
+
+
+def test_feature_freqs_log_spaced():
+    g = enc.feature_freqs(0.1, 10.0)
+    assert g[0] == pytest.approx(0.1) and g[-1] == pytest.approx(10.0)
+    np.testing.assert_allclose(np.diff(np.log(g)), np.log(100.0) / 31, rtol=1e-12)
+
+
+def test_bins():
+    edges = enc.bin_edges(0.1, 10.0)
+    mids = np.sqrt(edges[:-1] * edges[1:])
+    np.testing.assert_array_equal(enc.bin_of(mids, 0.1, 10.0), np.arange(enc.BINS))
+    assert enc.bin_of(0.05, 0.1, 10.0) == 0 and enc.bin_of(20.0, 0.1, 10.0) == enc.BINS - 1
+
+
+def test_forward_matches_point_loop():
+    feats, _ = _batch(2)
+    params = enc.init_params(1)
+    p = enc.unpack(params)
+    logits, _ = enc.forward(params, feats)
+    for o, x in enumerate(feats):
+        acc = np.zeros(enc.H2)
+        for i in range(x.shape[0]):
+            h1 = [max(0.0, sum(x[i, k] * p["w1"][k, j] for k in range(enc.K1)))
+                  for j in range(enc.H1)]
+            for j in range(enc.H2):
+                acc[j] += max(0.0, sum(h1[k] * p["w2"][k, j] for k in range(enc.H1)) + p["b2"][j])
+        emb = acc / x.shape[0]
+        for b in (0, 17, 1023):
+            ref = sum(emb[k] * p["w3"][k, b] for k in range(enc.H2)) + p["b3"][b]
+            assert logits[o, b] == pytest.approx(ref, rel=1e-12, abs=1e-12)
+
+
+def test_gradient_finite_differences():
+    feats, labels = _batch()
+    params = enc.init_params(2) + np.random.default_rng(3).normal(0, 0.01, enc.N_PARAMS)
+    loss, g = enc.loss_and_grad(params, feats, labels)
+    assert np.isfinite(loss)
+    rng = np.random.default_rng(4)
+    # probe coordinates in every parameter block
+    offs = np.cumsum([0] + [int(np.prod(s)) for _, s in enc.SHAPES])
+    idx = np.concatenate([rng.integers(offs[i], offs[i + 1], 6) for i in range(len(enc.SHAPES))])
+    h = 1e-6
+    for i in idx:
+        e = np.zeros(enc.N_PARAMS)
+        e[i] = h
+        lp, _ = enc.loss_and_grad(params + e, feats, labels)
+        lm, _ = enc.loss_and_grad(params - e, feats, labels)
+        fd = (lp - lm) / (2 * h)
+        assert g[i] == pytest.approx(fd, rel=1e-5, abs=1e-9), i
+
+
+def test_loss_uniform_logits():
+    feats, labels = _batch()
+    params = np.zeros(enc.N_PARAMS)
+    loss, g = enc.loss_and_grad(params, feats, labels)
+    assert loss == pytest.approx(np.log(enc.BINS), rel=1e-14)
+    gb3 = enc.unpack(g)["b3"]
+    ref = np.full(enc.BINS, 1.0 / enc.BINS) - np.bincount(labels, minlength=enc.BINS) / len(labels)
+    np.testing.assert_allclose(gb3, ref, atol=1e-15)
+
+
+def test_adam_first_step():
+    rng = np.random.default_rng(0)
+    p = rng.normal(size=100)
+    g = rng.normal(size=100)
+    p1, m, v = enc.adam_step(p, g, np.zeros(100), np.zeros(100), 1, 1e-3, eps=0.0)
+    np.testing.assert_allclose(p - p1, 1e-3 * np.sign(g), rtol=1e-12)
+
+
+# ---- search-and-refine reference -------------------------------------------
+
+from oracle import refine as ref  # noqa: E402
+
+
+@pytest.mark.parametrize("grid", [(0.1, 10.0, 2000), (0.05, 20.0, 50000), (0.01, 20.0, 7777)])
+def test_bin_table_against_edges(grid):
+    fmin, fmax, nf = grid
+    tab = ref.bin_table(*grid)
+    assert tab[0] == 0 and tab[-1] == nf and np.all(np.diff(tab) >= 0)
+    edges = ref.bin_edges(fmin, fmax)
+    f = ref.grid_f(fmin, fmax, nf, np.arange(nf))
+    # every frequency lies in [E_b, E_{b+1}) of the bin the table gives it
+    b_of_k = np.repeat(np.arange(ref.BINS), np.diff(tab))
+    assert b_of_k.size == nf
+    assert np.all(edges[b_of_k] <= f) and np.all(f < edges[b_of_k + 1])
+
+
+@pytest.mark.parametrize("grid", [(0.1, 10.0, 2000), (0.05, 20.0, 50000), (0.01, 20.0, 7777)])
+def test_library_bin_table_matches_reference(grid):
+    import paper_2111_07396_amd as ssg
+    np.testing.assert_array_equal(ssg.bin_table(grid), ref.bin_table(*grid))
+
+
+def test_top_bins_order_and_nan():
+    s = np.zeros(ref.BINS)
+    s[[5, 9, 700]] = [3.0, 3.0, 4.0]
+    s[11] = np.nan
+    assert ref.top_bins(s, 3) == [700, 5, 9]
+    assert ref.top_bins(s, 5)[3:] == [0, 1]  # ties at 0 in bin order; NaN ranks last
+    assert ref.top_bins(s, ref.BINS)[-1] == 11
+
+
+def test_refine_set_union_and_margin():
+    tab = ref.bin_table(0.1, 10.0, 20000)
+    s = np.zeros(ref.BINS)
+    s[[100, 101, 500]] = [5.0, 4.0, 3.0]
+    ks = ref.refine_set(s, 3, 1, tab)
+    want = np.concatenate([np.arange(tab[99], tab[103]), np.arange(tab[499], tab[502])])
+    np.testing.assert_array_equal(ks, want)
+    assert ref.refine_set(s, ref.BINS, 0, tab).size == 20000
+
+
+def test_refine_contains_full_best():
+    from paper_2111_07396_amd import synth
+    import oracle
+    cat = synth.make_catalog(11, 3, 60, 200.0, (0.5, 5.0), 0.05)
+    grid = (0.1, 10.0, 400)
+    pg, st = oracle.periodogram(oracle.SS, cat.offsets, cat.t, cat.y, cat.e, *grid)
+    table = ref.bin_table(*grid)
+    scores = np.random.default_rng(0).normal(size=(3, ref.BINS))
+    for o in range(3):
+        kb = int(np.nanargmax(pg[o]))
+        b = int(np.searchsorted(table, kb, side="right") - 1)
+        scores[o, b] = 100.0  # the bin of the full-grid best is proposed first
+    bi, bp = ref.refine_best(oracle.SS, cat.offsets, cat.t, cat.y, cat.e, grid, scores, 4, 0)
+    for o in range(3):
+        assert bi[o] == int(np.nanargmax(pg[o]))
+        assert bp[o] == pg[o, bi[o]]
