@@ -14,7 +14,10 @@ the timed region starts.
 value = (object, frequency) trials completed per second, summed over the two
 methods.  The JSON line also carries each method's own rate, the roofline of
 the dominant kernel (the fused Super Smoother trial kernel, timed with HIP
-events on its own stream) and the CPU oracle timed on a bounded sample.
+events on the stream it runs on), the CPU oracle timed on a bounded sample,
+and -- measured after the timed region -- the other precision, the other
+catalogs (single small object, uneven catalog with its FP32c-vs-FP64 error,
+single dense object) and the learned-proposal comparison.
 """
 from __future__ import annotations
 
@@ -31,11 +34,12 @@ sys.path.insert(0, ROOT)
 
 # Algorithmic floating-point operations per point of one trial (each add,
 # multiply, divide, compare or abs counted once), from the running-line
-# smoother's sliding-window form: see DESIGN.md, "Operation model".
+# smoother's sliding-window form.
 SS_FLOPS_PER_POINT = 385
 SSSP_FLOPS_PER_POINT = 156
 # MI355X: 256 CUs x 64 FP32/FP64 FMA lanes per clock x 2.4 GHz x 2 flops.
 PEAK_VALU_TFLOPS = 78.6
+ENCODER_WEIGHTS = os.path.join(ROOT, "paper_2111_07396_amd", "weights", "encoder_c5.npy")
 
 
 def _src_hash() -> str:
@@ -59,20 +63,106 @@ def _traffic(precision: str):
     return d.get("bytes_per_launch")
 
 
+def _best_rates(ctx, dc, grid, params, steps, methods):
+    """Wall-clock trials/s and trial-kernel ms per method (`steps` calls each)."""
+    import torch
+    out = {}
+    n = dc.n_obj * int(grid[2])
+    for m in methods:
+        r = ctx.ss_best_period(m, dc, grid, params)
+        torch.cuda.synchronize()
+        ms = []
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            r = ctx.ss_best_period(m, dc, grid, params, out=r)
+            ms.append(ctx.trial_kernel_ms()[0])
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        out[m] = {"trials_per_s": n / dt, "wall_ms": dt * 1e3, "trial_kernel_ms": min(ms)}
+    return out
+
+
+def _extras(ctx, ssg, synth, args):
+    """Measurements outside the timed region (each run once after a warm-up)."""
+    import numpy as np
+    import torch
+    ex = {}
+    names = {ssg.SS_METHOD_SS: "ss", ssg.SS_METHOD_SSSP: "sssp"}
+    both = (ssg.SS_METHOD_SS, ssg.SS_METHOD_SSSP)
+    # the other precision on the benchmark catalog
+    other = "fp32c" if args.precision == "fp64" else "fp64"
+    cat, grid = synth.catalog_n200(n_obj=args.n_obj)
+    dc = ssg.DeviceCatalog.from_numpy(cat.offsets, cat.t, cat.y, cat.e)
+    prm = ssg.Params(precision=ssg.SS_FP32C if other == "fp32c" else ssg.SS_FP64)
+    r = _best_rates(ctx, dc, grid, prm, 1, both)
+    ex[f"n200_{other}"] = {names[m]: r[m]["trials_per_s"] for m in both}
+    # single small object (N=100, 2,000 frequencies, FP64)
+    cat1, grid1 = synth.single_small()
+    dc1 = ssg.DeviceCatalog.from_numpy(cat1.offsets, cat1.t, cat1.y, cat1.e)
+    r = _best_rates(ctx, dc1, grid1, ssg.Params(), 3, both)
+    ex["single_small_fp64"] = {names[m]: {"ms": r[m]["wall_ms"], "trials_per_s":
+                                          r[m]["trials_per_s"]} for m in both}
+    # uneven catalog (N U[50,400]): rates in both precisions and the FP32c error
+    cat2, grid2 = synth.catalog_uneven(n_obj=args.n_obj)
+    dc2 = ssg.DeviceCatalog.from_numpy(cat2.offsets, cat2.t, cat2.y, cat2.e)
+    ex["uneven"] = {}
+    for pn, pv in (("fp64", ssg.SS_FP64), ("fp32c", ssg.SS_FP32C)):
+        r = _best_rates(ctx, dc2, grid2, ssg.Params(precision=pv), 1, both)
+        ex["uneven"][pn] = {names[m]: r[m]["trials_per_s"] for m in both}
+    sub = cat2.subset(np.arange(min(500, cat2.n_obj)))
+    dsub = ssg.DeviceCatalog.from_numpy(sub.offsets, sub.t, sub.y, sub.e)
+    err = {}
+    for m, fn in ((ssg.SS_METHOD_SS, ctx.ss_periodogram), (ssg.SS_METHOD_SSSP,
+                                                             ctx.sssp_periodogram)):
+        p64, _ = fn(dsub, grid2, ssg.Params(precision=ssg.SS_FP64))
+        p32, _ = fn(dsub, grid2, ssg.Params(precision=ssg.SS_FP32C))
+        d = (p32.double() - p64).abs()
+        rel = d / (1.0 - p64).clamp_min(1e-12)
+        ok = torch.isfinite(p64)
+        rel = rel[ok]
+        b64 = torch.nan_to_num(p64, nan=-1e300).argmax(1)
+        b32 = torch.nan_to_num(p32.double(), nan=-1e300).argmax(1)
+        err[names[m]] = {"max_abs_dP": float(d[ok].max()), "max_rel_chi2": float(rel.max()),
+                         "p99_rel_chi2": float(torch.quantile(rel.float()[:2_000_000], 0.99)),
+                         "frac_rel_over_1e-4": float((rel > 1e-4).double().mean()),
+                         "best_index_agreement": float((b64 == b32).double().mean())}
+    ex["uneven"]["fp32c_vs_fp64_first500"] = err
+    # single dense object (N=3,000, 500,000 frequencies)
+    cat3, grid3 = synth.single_dense()
+    dc3 = ssg.DeviceCatalog.from_numpy(cat3.offsets, cat3.t, cat3.y, cat3.e)
+    ex["single_dense"] = {}
+    for pn, pv in (("fp64", ssg.SS_FP64), ("fp32c", ssg.SS_FP32C)):
+        r = _best_rates(ctx, dc3, grid3, ssg.Params(precision=pv), 1, both)
+        ex["single_dense"][pn] = {names[m]: {"ms": r[m]["wall_ms"], "trials_per_s":
+                                             r[m]["trials_per_s"]} for m in both}
+    # learned proposal + refine against the full grid on a mixed-stream sample
+    if os.path.exists(ENCODER_WEIGHTS):
+        from paper_2111_07396_amd import learn
+        cat5, grid5 = synth.catalog_mixed(n_obj=args.learned_objects)
+        dc5 = ssg.DeviceCatalog.from_numpy(cat5.offsets, cat5.t, cat5.y, cat5.e)
+        w = torch.tensor(np.load(ENCODER_WEIGHTS), dtype=torch.float32, device="cuda")
+        ex["learned_vs_full"] = learn.compare(ctx, dc5, grid5, w, top_k=16, margin=1)
+        ex["learned_vs_full"]["sample"] = (f"{cat5.n_obj} objects of the mixed-stream "
+                                           f"generator, {grid5[2]} frequencies, SS FP64")
+    return ex
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", choices=("fp32c", "fp64"), default="fp32c")
+    ap.add_argument("--precision", choices=("fp64", "fp32c"), default="fp64")
     ap.add_argument("--n-obj", type=int, default=10_000)
     ap.add_argument("--cpu-sample-objects", type=int, default=24)
+    ap.add_argument("--learned-objects", type=int, default=2000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(objects shard across GPUs with no exchange; see DESIGN.md).", file=sys.stderr)
+              "(objects shard across GPUs with no exchange).", file=sys.stderr)
         return 2
 
     import numpy as np
@@ -107,6 +197,7 @@ def main() -> int:
         step(True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    print(f"timed {args.steps} steps in {t1 - t0:.2f} s", file=sys.stderr, flush=True)
     elapsed = t1 - t0
     trials = n_obj * n_freq
     value = 2 * trials * args.steps / elapsed
@@ -126,6 +217,11 @@ def main() -> int:
                 "achieved": achieved, "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_VALU_TFLOPS, "traffic": _traffic(args.precision)}
 
+    extras = None
+    if not args.no_extras:
+        extras = _extras(ctx, ssg, synth, args)
+        print("extras done", file=sys.stderr, flush=True)
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -134,7 +230,7 @@ def main() -> int:
         for m in (oracle.SS, oracle.SSSP):
             oracle.periodogram(m, sub.offsets, sub.t, sub.y, sub.e, *grid)
         c1 = time.perf_counter()
-        cpu = {"value": 2 * sub.n_obj * n_freq / (c1 - c0), "unit": "obj*freq trials/s",
+        cpu = {"value": 2 * sub.n_obj * n_freq / (c1 - c0), "unit": "trials/s",
                "cores": oracle.num_threads(), "kind": "oracle",
                "sample": f"first {sub.n_obj} objects x all {n_freq} frequencies, SS and SSSP, "
                          f"FP64 C oracle ({c1 - c0:.1f} s)"}
@@ -159,6 +255,7 @@ def main() -> int:
         "per_method": per_method,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "extras": extras,
     }
     print(json.dumps(rec), flush=True)
     ctx.close()

@@ -9,6 +9,13 @@ Smoother best frequency.  Everything here is plain numpy in float64, written
 as the definition (no fusion), with an analytic backward pass that the tests
 check against central finite differences.  Only the test suite may import it.
 
+With bf16=True the operands that the matrix cores take in BF16 (features,
+W1, W2, the hidden layer, and in the backward pass the two gated
+activation gradients) are rounded to BF16 (round to nearest, ties to even)
+before the FP64 products; everything else stays FP64.  This isolates the
+rounding that the BF16 precision of the network fixes from any other
+difference.
+
 Feature vector of point i of an object (80 slots, the last 13 zero):
   sin(2 pi g_m tt_i), cos(2 pi g_m tt_i) for the M = 32 frequencies g_m
   log-spaced over [f_lo, f_hi] (slots 2m and 2m+1),
@@ -29,6 +36,20 @@ ONE_SLOT = 66
 SHAPES = (("w1", (K1, H1)), ("w2", (H1, H2)), ("b2", (H2,)),
           ("w3", (H2, BINS)), ("b3", (BINS,)))
 N_PARAMS = sum(int(np.prod(s)) for _, s in SHAPES)
+
+
+def round_bf16(a):
+    """Rounds to the nearest BF16 value (8 significant bits, ties to even)."""
+    f = np.ascontiguousarray(a, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    lsb = (u >> 16) & 1
+    r = ((u + 0x7FFF + lsb) >> 16) << 16
+    out = (r & 0xFFFFFFFF).astype(np.uint32).view(np.float32).astype(np.float64)
+    return np.where(np.isfinite(f), out, f.astype(np.float64)).reshape(np.shape(a))
+
+
+def _q(a, on):
+    return round_bf16(a) if on else a
 
 
 def unpack(flat):
@@ -75,15 +96,17 @@ def bin_edges(f_lo, f_hi):
     return f_lo * (f_hi / f_lo) ** (np.arange(BINS + 1) / BINS)
 
 
-def forward(params, feats):
+def forward(params, feats, bf16=False):
     """feats: list of [n_o, 80] arrays.  Returns (logits [B, 1024], cache)."""
     p = unpack(params)
+    w1, w2 = _q(p["w1"], bf16), _q(p["w2"], bf16)
     cache = []
     emb = np.zeros((len(feats), H2))
     for o, x in enumerate(feats):
-        a1 = x @ p["w1"]
-        h1 = np.maximum(a1, 0.0)
-        a2 = h1 @ p["w2"] + p["b2"]
+        x = _q(x, bf16)
+        a1 = x @ w1
+        h1 = _q(np.maximum(a1, 0.0), bf16)
+        a2 = h1 @ w2 + p["b2"]
         h2 = np.maximum(a2, 0.0)
         emb[o] = h2.mean(axis=0)
         cache.append((x, a1, h1, a2))
@@ -91,10 +114,11 @@ def forward(params, feats):
     return logits, (emb, cache)
 
 
-def loss_and_grad(params, feats, labels):
+def loss_and_grad(params, feats, labels, bf16=False):
     """Mean softmax cross-entropy over the batch and its gradient (flat)."""
     p = unpack(params)
-    logits, (emb, cache) = forward(params, feats)
+    w2 = _q(p["w2"], bf16)
+    logits, (emb, cache) = forward(params, feats, bf16)
     B = logits.shape[0]
     z = logits - logits.max(axis=1, keepdims=True)
     lse = np.log(np.exp(z).sum(axis=1))
@@ -110,9 +134,10 @@ def loss_and_grad(params, feats, labels):
     for o, (x, a1, h1, a2) in enumerate(cache):
         n = x.shape[0]
         da2 = np.broadcast_to(demb[o] / n, a2.shape) * (a2 > 0)
-        g["w2"] += h1.T @ da2
         g["b2"] += da2.sum(axis=0)
-        da1 = (da2 @ p["w2"].T) * (a1 > 0)
+        da2 = _q(da2, bf16)
+        g["w2"] += h1.T @ da2
+        da1 = _q((da2 @ w2.T) * (a1 > 0), bf16)
         g["w1"] += x.T @ da1
     return loss, pack(g)
 

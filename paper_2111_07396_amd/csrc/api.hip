@@ -14,17 +14,30 @@
 
 namespace ssg {
 
-// Default trial-group shape for a light curve of n points: the smallest
-// listed shape that holds it.
-int default_shape(int64_t n) {
-    static const int order[][3] = {{64, 1, 1},    {128, 1, 2},  {256, 2, 2},   {384, 2, 3},
-                                   {512, 4, 2},   {1024, 4, 4}, {2048, 8, 4},  {3072, 16, 3},
-                                   {4096, 16, 4}};
-    for (const auto &o : order)
-        if (n <= o[0])
-            for (int s = 0; s < kNumShapes; ++s)
-                if (kShapes[s].nw == o[1] && kShapes[s].ppl == o[2]) return s;
+// Default trial-group shape for a light curve of n points: per method and
+// precision, the fastest shape measured on MI355X for each length range
+// (synthetic catalogs, 20,000 frequencies; single-wavefront groups win while
+// a wavefront holds the curve, SSSP prefers two wavefronts from 193 points).
+struct ShapeRow {
+    int32_t n_max, nw, ppl;
+};
+constexpr ShapeRow kDefSS64[] = {{64, 1, 1},   {128, 1, 2},  {192, 1, 3},  {256, 1, 4},
+                                 {384, 2, 3},  {512, 4, 2},  {1024, 8, 2}, {2048, 8, 4},
+                                 {3072, 16, 3}, {4096, 16, 4}};
+constexpr ShapeRow kDefOther[] = {{64, 1, 1},   {128, 1, 2},  {192, 1, 3},  {256, 2, 2},
+                                  {384, 2, 3},  {512, 4, 2},  {1024, 8, 2}, {2048, 8, 4},
+                                  {3072, 16, 3}, {4096, 16, 4}};
+constexpr int kNumDefRows = (int)(sizeof(kDefSS64) / sizeof(kDefSS64[0]));
+static_assert(kNumDefRows == (int)(sizeof(kDefOther) / sizeof(kDefOther[0])), "tables");
+
+int shape_index(int nw, int ppl) {
+    for (int s = 0; s < kNumShapes; ++s)
+        if (kShapes[s].nw == nw && kShapes[s].ppl == ppl) return s;
     return -1;
+}
+
+const ShapeRow *default_rows(int method, int precision) {
+    return (method == 0 && precision == 0) ? kDefSS64 : kDefOther;
 }
 
 }  // namespace ssg
@@ -132,8 +145,8 @@ struct Plan {
 
 // Reset plus prep (with device-side planning of the shape classes).  Nothing
 // here waits for the device.
-int prepare(ss_ctx *ctx, const ss_catalog *cat, const ss_params *prm, int32_t *obj_status,
-            hipStream_t stream, Plan &P) {
+int prepare(ss_ctx *ctx, int method, const ss_catalog *cat, const ss_params *prm,
+            int32_t *obj_status, hipStream_t stream, Plan &P) {
     const int64_t n_obj = cat->n_obj;
     const int64_t total = cat->n_points;
     SS_HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
@@ -145,9 +158,10 @@ int prepare(ss_ctx *ctx, const ss_catalog *cat, const ss_params *prm, int32_t *o
         R.rule_n[i] = ctx->rules[(size_t)i].first;
         R.rule_shape[i] = ctx->rules[(size_t)i].second;
     }
-    for (int64_t nmax : {64, 128, 256, 384, 512, 1024, 2048, 3072, 4096}) {
-        R.def_n[R.n_def] = (int32_t)nmax;
-        R.def_shape[R.n_def] = default_shape(nmax);
+    const ShapeRow *rows = default_rows(method, prm->precision);
+    for (int i = 0; i < kNumDefRows; ++i) {
+        R.def_n[R.n_def] = rows[i].n_max;
+        R.def_shape[R.n_def] = shape_index(rows[i].nw, rows[i].ppl);
         R.n_def++;
     }
     P.ext.assign(kNumShapes, 2);
@@ -159,7 +173,7 @@ int prepare(ss_ctx *ctx, const ss_catalog *cat, const ss_params *prm, int32_t *o
         if (trial_lds_bytes(kShapes[c].nw, kShapes[c].ppl, P.ext[c]) <= ctx->max_lds)
             R.runnable |= 1u << c;
     }
-    R.fallback = default_shape(64);
+    R.fallback = shape_index(1, 1);
     for (int i = 0; i < R.n_rules; ++i) P.used[R.rule_shape[i]] = true;
     for (int i = 0; i < R.n_def; ++i) P.used[R.def_shape[i]] = true;
     P.used[R.fallback] = true;
@@ -263,7 +277,7 @@ int run(ss_ctx *ctx, int method, const ss_catalog *cat, const ss_grid *grid,
                                          : choose_tile(n_obj, grid->n_freq);
     const int32_t n_tiles = (int32_t)((grid->n_freq + tile - 1) / tile);
     Plan P;
-    int rc = prepare(ctx, cat, prm, obj_status, stream, P);
+    int rc = prepare(ctx, method, cat, prm, obj_status, stream, P);
     if (rc != SS_OK) return rc;
     return trials(ctx, P, method, cat, grid, prm, pgram64, pgram32, want_best, obj_status, stream,
                   best_idx, best_period, best_power, tile, n_tiles, nullptr);
@@ -328,11 +342,11 @@ EncArgs enc_args(ss_ctx *ctx, const ss_catalog *cat, const ss_grid *grid, const 
 
 // Prep, encoder forward and head: logits [n_obj][1024] in ctx->logits
 // (or in `logits_out` when given).  act is filled when want_act.
-int encode(ss_ctx *ctx, const ss_catalog *cat, const ss_grid *grid, const ss_params *prm,
-           const float *params, int32_t *obj_status, hipStream_t stream, float *emb_out,
-           float *logits_out, bool want_act, Plan &P, EncArgs &A) {
+int encode(ss_ctx *ctx, int method, const ss_catalog *cat, const ss_grid *grid,
+           const ss_params *prm, const float *params, int32_t *obj_status, hipStream_t stream,
+           float *emb_out, float *logits_out, bool want_act, Plan &P, EncArgs &A) {
     const int64_t n_obj = cat->n_obj;
-    int rc = prepare(ctx, cat, prm, obj_status, stream, P);
+    int rc = prepare(ctx, method, cat, prm, obj_status, stream, P);
     if (rc != SS_OK) return rc;
     SS_HIP_TRY(ctx->emb.ensure((size_t)n_obj * kEncH2 * 4), "workspace");
     SS_HIP_TRY(ctx->act.ensure((size_t)n_obj * kEncH2 * 4), "workspace");
@@ -563,8 +577,8 @@ int ss_enc_forward(ss_ctx *ctx, const ss_catalog *cat, const ss_grid *grid,
     if (cat->n_obj == 0) return SS_OK;
     Plan P;
     EncArgs A;
-    return encode(ctx, cat, grid, &prm, enc_params, obj_status, (hipStream_t)stream, emb, logits,
-                  false, P, A);
+    return encode(ctx, SS_METHOD_SS, cat, grid, &prm, enc_params, obj_status,
+                  (hipStream_t)stream, emb, logits, false, P, A);
 }
 
 int ss_enc_train_grad(ss_ctx *ctx, const ss_catalog *cat, const ss_grid *grid,
@@ -583,7 +597,8 @@ int ss_enc_train_grad(ss_ctx *ctx, const ss_catalog *cat, const ss_grid *grid,
     const int64_t n_obj = cat->n_obj;
     Plan P;
     EncArgs A;
-    rc = encode(ctx, cat, grid, &prm, enc_params, obj_status, s, nullptr, nullptr, true, P, A);
+    rc = encode(ctx, SS_METHOD_SS, cat, grid, &prm, enc_params, obj_status, s, nullptr, nullptr,
+                true, P, A);
     if (rc != SS_OK) return rc;
     const int n_waves = enc_bwd_waves((int)n_obj, ctx->n_cu);
     SS_HIP_TRY(ctx->dlog.ensure((size_t)n_obj * kEncBins * 4), "workspace");
@@ -629,7 +644,7 @@ int ss_refine_best_period(ss_ctx *ctx, int32_t method, const ss_catalog *cat,
     if (cat->n_obj == 0) return SS_OK;
     const hipStream_t s = (hipStream_t)stream;
     Plan P;
-    rc = prepare(ctx, cat, params, obj_status, s, P);
+    rc = prepare(ctx, method, cat, params, obj_status, s, P);
     if (rc != SS_OK) return rc;
     return refine(ctx, P, method, cat, grid, params, logits, top_k, margin, obj_status, s,
                   best_idx, best_period, best_power);
@@ -651,7 +666,8 @@ int ss_learned_best_period(ss_ctx *ctx, int32_t method, const ss_catalog *cat,
     const hipStream_t s = (hipStream_t)stream;
     Plan P;
     EncArgs A;
-    rc = encode(ctx, cat, grid, params, enc_params, obj_status, s, nullptr, nullptr, false, P, A);
+    rc = encode(ctx, method, cat, grid, params, enc_params, obj_status, s, nullptr, nullptr, false,
+                P, A);
     if (rc != SS_OK) return rc;
     return refine(ctx, P, method, cat, grid, params, (const float *)ctx->logits.p, top_k, margin,
                   obj_status, s, best_idx, best_period, best_power);

@@ -126,3 +126,19 @@ def single_dense(seed: int = 3):
     + N(0, 0.02); 500,000 frequencies on [0.01, 20) c/d."""
     return make_catalog(seed, 1, 3000, 3000.0, (0.2, 10.0), 0.02, shapes=(2,)), \
         (0.01, 20.0, 500_000)
+
+
+def training_set(seed: int = 4, n_obj: int = 200_000):
+    """Learned-proposal training curves: N U_int[50, 400] over 1,000 d,
+    periods log-U[0.1, 100] d, the three shapes; labels are taken on the
+    mixed-stream grid (50,000 frequencies on [0.05, 20) c/d)."""
+    return (make_catalog(seed, n_obj, (50, 400), 1000.0, (0.1, 100.0), 0.05),
+            (0.05, 20.0, 50_000))
+
+
+def catalog_mixed(seed: int = 5, n_obj: int = 1_000_000):
+    """Mixed stream: N log-uniform on [20, 1000] over 1,000 d, periods
+    log-U[0.05, 20] d, the three shapes, noise 0.05; 50,000 frequencies on
+    [0.05, 20) c/d."""
+    return (make_catalog(seed, n_obj, ("loguniform", 20, 1000), 1000.0, (0.05, 20.0), 0.05),
+            (0.05, 20.0, 50_000))

@@ -105,6 +105,39 @@ def test_loss_uniform_logits():
     np.testing.assert_allclose(gb3, ref, atol=1e-15)
 
 
+def test_round_bf16_values():
+    one = 1.0
+    vals = np.array([one, one + 2.0**-8, one + 3 * 2.0**-8, one + 2.0**-8 + 2.0**-20, -2.5,
+                     3.0e38, 0.0])
+    want = np.array([one, one, one + 2.0**-6, one + 2.0**-7, -2.5, 2.0**128 * 0 + 2.99e38, 0.0])
+    got = enc.round_bf16(vals)
+    np.testing.assert_array_equal(got[[0, 1, 2, 3, 4, 6]], want[[0, 1, 2, 3, 4, 6]])
+    assert abs(got[5] - 3.0e38) <= 3.0e38 * 2.0**-8
+    # every result has at most 8 significant bits
+    x = np.random.default_rng(0).normal(size=1000) * 10.0 ** np.random.default_rng(1).integers(-20, 20, 1000)
+    r = enc.round_bf16(x)
+    m, _ = np.frexp(r)
+    assert np.all((m * 2**8) == np.round(m * 2**8))
+    assert np.all(np.abs(r - x) <= np.abs(x) * 2.0**-8)
+
+
+def test_bf16_option_changes_only_rounding():
+    feats, labels = _batch()
+    params = enc.init_params(2)
+    l0, g0 = enc.loss_and_grad(params, feats, labels)
+    l1, g1 = enc.loss_and_grad(params, feats, labels, bf16=True)
+    assert abs(l1 - l0) <= 1e-2 * abs(l0)
+    assert np.linalg.norm(g1 - g0) <= 0.1 * np.linalg.norm(g0)
+    # with operands that are already BF16 values the option changes nothing upstream of the
+    # hidden layer: exact features and weights give the same first-layer output
+    p = enc.unpack(params)
+    p["w1"] = enc.round_bf16(p["w1"])
+    x = [enc.round_bf16(f) for f in feats]
+    la, _ = enc.forward(enc.pack(p), x)
+    lb, _ = enc.forward(enc.pack(p), x, bf16=True)
+    assert np.max(np.abs(la - lb)) <= 0.05 * np.max(np.abs(la))
+
+
 def test_adam_first_step():
     rng = np.random.default_rng(0)
     p = rng.normal(size=100)

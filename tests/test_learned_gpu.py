@@ -1,12 +1,16 @@
 """GPU parity of the learned proposal, through the C ABI.
 
 - Encoder forward (BF16 matrix-core per-point layers, FP32 head) and the
-  training gradient against the FP64 reference: relative Frobenius error
-  per tensor <= 2e-2.  BF16 keeps 8 significant bits (relative rounding
-  2^-9 = 2e-3 per operand); with the features, both weight matrices and the
-  hidden layer rounded once each, and ReLU gates that may flip for
-  pre-activations within a few rounding steps of zero, 2e-2 leaves an order
-  of magnitude of headroom over the expected ~2e-3.
+  training gradient, per tensor, in relative Frobenius norm:
+  (a) against the FP64 reference with the same operands rounded to BF16:
+      <= 2e-3 (what is left is FP32 accumulation order and the FP32
+      features, each ~1e-6, plus ReLU gates that flip for pre-activations
+      within an FP32 rounding of zero);
+  (b) against the plain FP64 definition: <= 2 x the error that the BF16
+      operand rounding alone causes (measured by (a)'s reference) + 2e-3.
+      BF16 keeps 8 significant bits (2^-9 relative per operand); the first
+      layer's weight gradient sums point terms of both signs, so its
+      relative error grows with the cancellation (a few percent here).
 - Adam against its definition (FP32 vs FP64: 1e-5 relative).
 - Refine against the FP64 refine reference on the same seeded logits: best
   index bit-exact (unless the reference's two best powers over the refined
@@ -22,7 +26,14 @@ import paper_2111_07396_amd as ssg
 from paper_2111_07396_amd import synth
 
 pytestmark = pytest.mark.gpu
-FROB = 2e-2
+FROB_EMUL = 2e-3
+
+
+def _check(gpu, pure, emul, what):
+    budget = _frob(emul, pure)
+    e_emul, e_pure = _frob(gpu, emul), _frob(gpu, pure)
+    assert e_emul <= FROB_EMUL, (what, e_emul)
+    assert e_pure <= 2 * budget + FROB_EMUL, (what, e_pure, budget)
 
 
 @pytest.fixture(scope="module")
@@ -68,12 +79,15 @@ def test_encoder_forward_matches_reference(ctx):
     emb, logits, st = ctx.enc_forward(dc, grid, pt)
     torch.cuda.synchronize()
     assert (st.cpu().numpy() == 0).all()
-    ref_logits, (ref_emb, _) = enc.forward(params, _feats(cat, grid))
-    assert _frob(emb.cpu().numpy(), ref_emb) <= FROB
-    assert _frob(logits.cpu().numpy(), ref_logits) <= FROB
+    feats = _feats(cat, grid)
+    ref_logits, (ref_emb, _) = enc.forward(params, feats)
+    emu_logits, (emu_emb, _) = enc.forward(params, feats, bf16=True)
+    e, lg = emb.cpu().numpy(), logits.cpu().numpy()
+    _check(e, ref_emb, emu_emb, "emb")
+    _check(lg, ref_logits, emu_logits, "logits")
     # per object, too (lengths 20..300 cover one to ten 32-point tiles)
     for o in range(cat.n_obj):
-        assert _frob(emb.cpu().numpy()[o], ref_emb[o]) <= FROB, o
+        _check(e[o], ref_emb[o], emu_emb[o], f"emb[{o}]")
 
 
 def test_encoder_skips_bad_objects(ctx):
@@ -102,11 +116,15 @@ def test_training_gradient_matches_reference(ctx):
     lt = torch.tensor(labels, dtype=torch.int32, device="cuda")
     grad, loss, st = ctx.enc_train_grad(dc, grid, pt, lt)
     torch.cuda.synchronize()
-    ref_loss, ref_grad = enc.loss_and_grad(params, _feats(cat, grid), labels)
-    assert abs(loss.item() - ref_loss) <= 1e-2 * abs(ref_loss)
-    g, r = enc.unpack(grad.cpu().numpy().astype(np.float64)), enc.unpack(ref_grad)
+    feats = _feats(cat, grid)
+    ref_loss, ref_grad = enc.loss_and_grad(params, feats, labels)
+    emu_loss, emu_grad = enc.loss_and_grad(params, feats, labels, bf16=True)
+    assert abs(loss.item() - emu_loss) <= 1e-4 * abs(emu_loss)
+    assert abs(loss.item() - ref_loss) <= 2 * abs(emu_loss - ref_loss) + 1e-4 * abs(ref_loss)
+    g = enc.unpack(grad.cpu().numpy().astype(np.float64))
+    r, m = enc.unpack(ref_grad), enc.unpack(emu_grad)
     for name, _ in enc.SHAPES:
-        assert _frob(g[name], r[name]) <= FROB, (name, _frob(g[name], r[name]))
+        _check(g[name], r[name], m[name], name)
     assert (g["w1"][enc.ONE_SLOT + 1:] == 0).all()
     # deterministic: a second call gives the same bits
     grad2, loss2, _ = ctx.enc_train_grad(dc, grid, pt, lt)
@@ -150,7 +168,9 @@ def test_refine_matches_reference(ctx, method, top_k, margin):
     for o in range(cat.n_obj):
         if o == 4:
             continue
-        assert bi_o[o] >= 0
+        if bi_o[o] < 0:  # every selected bin is narrower than the grid step: nothing to search
+            assert bi[o] == -1 and np.isnan(bw[o]), o
+            continue
         if bi[o] != bi_o[o]:
             ks = ref.refine_set(logits[o].astype(np.float64), top_k, margin, table)
             a, b = cat.offsets[o], cat.offsets[o + 1]
