@@ -135,15 +135,23 @@ def _extras(ctx, ssg, synth, args):
         r = _best_rates(ctx, dc3, grid3, ssg.Params(precision=pv), 1, both)
         ex["single_dense"][pn] = {names[m]: {"ms": r[m]["wall_ms"], "trials_per_s":
                                              r[m]["trials_per_s"]} for m in both}
-    # learned proposal + refine against the full grid on a mixed-stream sample
+    # proposal + exact refine against the full grid on a mixed-stream sample
+    from paper_2111_07396_amd import learn
+    cat5, grid5 = synth.catalog_mixed(n_obj=args.learned_objects)
+    dc5 = ssg.DeviceCatalog.from_numpy(cat5.offsets, cat5.t, cat5.y, cat5.e)
+    full5 = ctx.ss_best_period(ssg.SS_METHOD_SS, dc5, grid5)
+    pol = dict(learn.POLICY)
+    rl = {"sample": f"{cat5.n_obj} objects of the mixed-stream generator (N log-uniform "
+                    f"[20, 1000]), {grid5[2]} frequencies on [{grid5[0]}, {grid5[1]}), SS FP64",
+          "policy": pol}
+    rl["bin_scores_then_refine"] = learn.compare(ctx, dc5, grid5, None, full=full5, **pol)
     if os.path.exists(ENCODER_WEIGHTS):
-        from paper_2111_07396_amd import learn
-        cat5, grid5 = synth.catalog_mixed(n_obj=args.learned_objects)
-        dc5 = ssg.DeviceCatalog.from_numpy(cat5.offsets, cat5.t, cat5.y, cat5.e)
         w = torch.tensor(np.load(ENCODER_WEIGHTS), dtype=torch.float32, device="cuda")
-        ex["learned_vs_full"] = learn.compare(ctx, dc5, grid5, w, top_k=16, margin=1)
-        ex["learned_vs_full"]["sample"] = (f"{cat5.n_obj} objects of the mixed-stream "
-                                           f"generator, {grid5[2]} frequencies, SS FP64")
+        rl["encoder_plus_100x_bin_scores"] = learn.compare(
+            ctx, dc5, grid5, w, 100.0, pol["top_k"], pol["margin"], pol["full_below"], full=full5)
+        rl["encoder_only"] = learn.compare(ctx, dc5, grid5, w, 0.0, pol["top_k"], pol["margin"],
+                                           pol["full_below"], full=full5)
+    ex["proposal_vs_full"] = rl
     return ex
 
 

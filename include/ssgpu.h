@@ -222,19 +222,37 @@ int ss_adam_step(float *params, const float *grad, float *m, float *v, int64_t n
  * bins by logit (NaN ranks lowest; equal logits: lower bin first), each
  * widened by `margin` bins on both sides, are searched at every grid
  * frequency they hold, and the best over that set is reported exactly as
- * ss_best_period reports it (lowest index among equal powers).  1 <= top_k
- * <= 1024, 0 <= margin <= 64. */
+ * ss_best_period reports it (lowest index among equal powers).  Objects with
+ * fewer than full_below points are searched on the whole grid instead (0 =
+ * never).  1 <= top_k <= 1024, 0 <= margin <= 64, full_below >= 0. */
 int ss_refine_best_period(ss_ctx *ctx, int32_t method, const ss_catalog *cat,
                           const ss_grid *grid, const ss_params *params, const float *logits,
-                          int32_t top_k, int32_t margin, int64_t *best_idx, double *best_period,
-                          double *best_power, int32_t *obj_status, void *stream);
+                          int32_t top_k, int32_t margin, int32_t full_below, int64_t *best_idx,
+                          double *best_period, double *best_power, int32_t *obj_status,
+                          void *stream);
 
-/* Encoder forward + refine in one call.  The first call on a new grid uploads
- * the bin table synchronously. */
+/* Cheap exact-grid proposal scores [n_obj][1024] (device FP32): for every grid
+ * frequency, the light curve is folded (FP64 phase, as for the trials) into
+ * B = clamp(n / 5, 4, 32) equal phase bins and scored by the fraction of chi0
+ * explained by the bins' weighted means, sum_b (sum_{i in b} w_i yc_i)^2 /
+ * (sum_{i in b} w_i) / chi0 with yc = y - ybar (FP32 sums, FP64 phase and
+ * bin index); each log bin gets the maximum over its grid frequencies (0 if
+ * it holds none; all 0 for objects with a nonzero status).  A phase-
+ * dispersion statistic: no sort, no smoother. */
+int ss_bin_scores(ss_ctx *ctx, const ss_catalog *cat, const ss_grid *grid, float *scores,
+                  int32_t *obj_status, void *stream);
+
+/* Proposal + exact refine in one call.  The bins are ranked by
+ * logit_b + gamma * score_b, where logit_b comes from the encoder
+ * (enc_params; NULL = no encoder, logits 0) and score_b from ss_bin_scores
+ * (gamma = 0: not computed).  gamma >= 0; at least one of the two terms must
+ * be present.  top_k, margin and full_below as for ss_refine_best_period.
+ * The first call on a new grid uploads the bin table synchronously. */
 int ss_learned_best_period(ss_ctx *ctx, int32_t method, const ss_catalog *cat,
                            const ss_grid *grid, const ss_params *params, const float *enc_params,
-                           int32_t top_k, int32_t margin, int64_t *best_idx, double *best_period,
-                           double *best_power, int32_t *obj_status, void *stream);
+                           float gamma, int32_t top_k, int32_t margin, int32_t full_below,
+                           int64_t *best_idx, double *best_period, double *best_power,
+                           int32_t *obj_status, void *stream);
 
 /* Message for the last failing call on this host thread ("" if none). */
 const char *ss_last_error(void);

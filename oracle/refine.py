@@ -55,9 +55,10 @@ def refine_set(scores, top_k, margin, table):
     return np.concatenate(ks).astype(np.int64) if ks else np.zeros(0, dtype=np.int64)
 
 
-def refine_best(method, offsets, t, y, e, grid, scores, top_k, margin, alpha=9.0):
+def refine_best(method, offsets, t, y, e, grid, scores, top_k, margin, alpha=9.0, full_below=0):
     """(best_idx, best_power) per object; -1 / NaN for objects with a bad
-    status or an empty selection."""
+    status or an empty selection.  Objects with fewer than full_below points
+    are searched on the whole grid."""
     fmin, fmax, n_freq = grid
     table = bin_table(fmin, fmax, n_freq)
     n_obj = len(offsets) - 1
@@ -65,7 +66,10 @@ def refine_best(method, offsets, t, y, e, grid, scores, top_k, margin, alpha=9.0
     bp = np.full(n_obj, np.nan)
     for o in range(n_obj):
         a, b = offsets[o], offsets[o + 1]
-        ks = refine_set(scores[o], top_k, margin, table)
+        if b - a < full_below:
+            ks = np.arange(n_freq, dtype=np.int64)
+        else:
+            ks = refine_set(scores[o], top_k, margin, table)
         if ks.size == 0:
             continue
         pg, st = periodogram(method, np.array([0, b - a]), t[a:b], y[a:b], e[a:b], fmin, fmax,
@@ -81,3 +85,35 @@ def refine_best(method, offsets, t, y, e, grid, scores, top_k, margin, alpha=9.0
             bi[o] = ks[best]
             bp[o] = row[best]
     return bi, bp
+
+
+def bin_scores(t, y, e, grid):
+    """Cheap exact-grid proposal score per log bin (zeros for a bad object):
+    at every grid frequency the fraction of chi0 explained by the weighted
+    means of B = clamp(n // 5, 4, 32) equal phase bins, phase = frac(tt f) in
+    FP64, bin = min(B - 1, floor(phase B)); each log bin takes the maximum
+    over its grid frequencies (0 when it holds none)."""
+    from . import prep
+    fmin, fmax, n_freq = grid
+    st, tt, w, ybar, chi0 = prep(t, y, e)
+    out = np.zeros(BINS)
+    if st != 0:
+        return out
+    n = len(t)
+    B = min(32, max(4, n // 5))
+    yc = np.asarray(y, dtype=np.float64) - ybar
+    f = grid_f(fmin, fmax, n_freq, np.arange(n_freq))
+    score = np.empty(n_freq)
+    for k0 in range(0, n_freq, 512):
+        q = np.outer(f[k0:k0 + 512], tt)
+        jb = np.minimum(B - 1, np.floor((q - np.floor(q)) * B).astype(np.int64))
+        for r in range(jb.shape[0]):
+            W = np.bincount(jb[r], weights=w, minlength=B)
+            S = np.bincount(jb[r], weights=w * yc, minlength=B)
+            ok = W > 0
+            score[k0 + r] = np.sum(S[ok] ** 2 / W[ok]) / chi0
+    tab = bin_table(fmin, fmax, n_freq)
+    for b in range(BINS):
+        if tab[b + 1] > tab[b]:
+            out[b] = score[tab[b]:tab[b + 1]].max()
+    return out

@@ -30,7 +30,7 @@ EXPORTED = ("ss_params_default", "ss_ctx_create", "ss_ctx_destroy", "ss_periodog
             "ss_ctx_set_shape", "ss_ctx_set_tile", "ss_ctx_set_timing", "ss_ctx_trial_kernel_ms",
             "ss_last_error", "ss_version", "ss_bin_table", "ss_enc_num_params", "ss_enc_forward",
             "ss_enc_train_grad", "ss_adam_step", "ss_refine_best_period",
-            "ss_learned_best_period")
+            "ss_learned_best_period", "ss_bin_scores")
 ENC_PARAMS = 145536
 ENC_BINS = 1024
 
@@ -126,11 +126,17 @@ def load_library(path: str = LIB_PATH):
     lib.ss_adam_step.argtypes = [vp, vp, vp, vp, i64, i32, ctypes.c_float, ctypes.c_float,
                                  ctypes.c_float, ctypes.c_float, vp]
     lib.ss_adam_step.restype = ctypes.c_int
-    for name in ("ss_refine_best_period", "ss_learned_best_period"):
-        f = getattr(lib, name)
-        f.argtypes = [vp, i32, ctypes.POINTER(_Catalog), ctypes.POINTER(_Grid),
-                      ctypes.POINTER(_Params), vp, i32, i32, vp, vp, vp, vp, vp]
-        f.restype = ctypes.c_int
+    lib.ss_refine_best_period.argtypes = [vp, i32, ctypes.POINTER(_Catalog),
+                                          ctypes.POINTER(_Grid), ctypes.POINTER(_Params), vp,
+                                          i32, i32, i32, vp, vp, vp, vp, vp]
+    lib.ss_refine_best_period.restype = ctypes.c_int
+    lib.ss_learned_best_period.argtypes = [vp, i32, ctypes.POINTER(_Catalog),
+                                           ctypes.POINTER(_Grid), ctypes.POINTER(_Params), vp,
+                                           ctypes.c_float, i32, i32, i32, vp, vp, vp, vp, vp]
+    lib.ss_learned_best_period.restype = ctypes.c_int
+    lib.ss_bin_scores.argtypes = [vp, ctypes.POINTER(_Catalog), ctypes.POINTER(_Grid), vp, vp,
+                                  vp]
+    lib.ss_bin_scores.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -350,8 +356,8 @@ class Context:
                                       _ptr(st), _stream_ptr(stream)))
         return grad, loss, st
 
-    def refine_best_period(self, method, cat, grid, logits, top_k=16, margin=1, params=None,
-                           out=None, stream=None):
+    def refine_best_period(self, method, cat, grid, logits, top_k=16, margin=1, full_below=0,
+                           params=None, out=None, stream=None):
         """Exact search over the fine-grid frequencies of each object's top bins."""
         params = params or Params()
         n_obj = cat.n_obj
@@ -362,22 +368,36 @@ class Context:
         p = params._c()
         _check(_lib.ss_refine_best_period(self._h, int(method), ctypes.byref(c), ctypes.byref(g),
                                           ctypes.byref(p), _ptr(logits), int(top_k), int(margin),
-                                          _ptr(bi), _ptr(bp), _ptr(bw), _ptr(st),
+                                          int(full_below), _ptr(bi), _ptr(bp), _ptr(bw), _ptr(st),
                                           _stream_ptr(stream)))
         return bi, bp, bw, st
 
-    def learned_best_period(self, method, cat, grid, enc_params, top_k=16, margin=1, params=None,
-                            out=None, stream=None):
-        """Encoder proposal + exact refine in one call."""
+    def bin_scores(self, cat, grid, stream=None):
+        """(scores [n_obj, 1024], status): the cheap exact-grid proposal score per log bin."""
+        n_obj = cat.n_obj
+        dev = cat.offsets.device
+        sc = torch.empty((n_obj, ENC_BINS), dtype=torch.float32, device=dev)
+        st = torch.empty(n_obj, dtype=torch.int32, device=dev)
+        g = _Grid(float(grid[0]), float(grid[1]), int(grid[2]))
+        c = cat._c()
+        _check(_lib.ss_bin_scores(self._h, ctypes.byref(c), ctypes.byref(g), _ptr(sc), _ptr(st),
+                                  _stream_ptr(stream)))
+        return sc, st
+
+    def learned_best_period(self, method, cat, grid, enc_params=None, gamma=0.0, top_k=16,
+                            margin=1, full_below=0, params=None, out=None, stream=None):
+        """Proposal (encoder logits + gamma x bin scores) + exact refine in one call."""
         params = params or Params()
         n_obj = cat.n_obj
-        _f32_dev(enc_params, ENC_PARAMS, "enc_params")
+        if enc_params is not None:
+            _f32_dev(enc_params, ENC_PARAMS, "enc_params")
         bi, bp, bw, st = self._best_out(n_obj, cat.offsets.device, out)
         g = _Grid(float(grid[0]), float(grid[1]), int(grid[2]))
         c = cat._c()
         p = params._c()
+        ep = _ptr(enc_params) if enc_params is not None else ctypes.c_void_p(None)
         _check(_lib.ss_learned_best_period(self._h, int(method), ctypes.byref(c),
-                                           ctypes.byref(g), ctypes.byref(p), _ptr(enc_params),
-                                           int(top_k), int(margin), _ptr(bi), _ptr(bp), _ptr(bw),
-                                           _ptr(st), _stream_ptr(stream)))
+                                           ctypes.byref(g), ctypes.byref(p), ep, float(gamma),
+                                           int(top_k), int(margin), int(full_below), _ptr(bi),
+                                           _ptr(bp), _ptr(bw), _ptr(st), _stream_ptr(stream)))
         return bi, bp, bw, st

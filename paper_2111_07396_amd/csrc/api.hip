@@ -82,7 +82,7 @@ struct DevBuf {
 struct ss_ctx {
     int device = 0;
     DevBuf tt, w, yc, w32, yc32, chi0, sw, objs, counts, queues, part_p, part_k;
-    DevBuf emb, act, logits, dlog, loss_o, dE, partial, ranges, bin_k;
+    DevBuf emb, act, logits, dlog, loss_o, dE, partial, ranges, bin_k, scores;
     double bin_grid[3] = {0.0, 0.0, 0.0};  // grid whose bin table is in bin_k
     int max_lds = 65536;
     int n_cu = 1;
@@ -364,8 +364,9 @@ int encode(ss_ctx *ctx, int method, const ss_catalog *cat, const ss_grid *grid,
 // Refine: the planner turns logits into per-object fine-grid ranges and the
 // trial kernel searches only those.
 int refine(ss_ctx *ctx, const Plan &P, int method, const ss_catalog *cat, const ss_grid *grid,
-           const ss_params *prm, const float *logits, int top_k, int margin, int32_t *obj_status,
-           hipStream_t stream, int64_t *best_idx, double *best_period, double *best_power) {
+           const ss_params *prm, const float *logits, const float *scores, float gamma,
+           int top_k, int margin, int full_below, int32_t *obj_status, hipStream_t stream,
+           int64_t *best_idx, double *best_period, double *best_power) {
     const int64_t n_obj = cat->n_obj;
     int rc = upload_bin_table(ctx, grid);
     if (rc != SS_OK) return rc;
@@ -381,19 +382,44 @@ int refine(ss_ctx *ctx, const Plan &P, int method, const ss_catalog *cat, const 
     for (int i = 0; i < n_sel; ++i) max_len += widths[i];
     max_len = std::min<int64_t>(max_len, grid->n_freq);
     const int32_t chunk = 128;
-    const int64_t n_rng64 = top_k + (max_len + chunk - 1) / chunk;
+    int64_t n_rng64 = top_k + (max_len + chunk - 1) / chunk;
+    if (full_below > 0) n_rng64 = std::max<int64_t>(n_rng64, (grid->n_freq + chunk - 1) / chunk);
     if (n_rng64 > INT32_MAX / 2) return fail(SS_ERR_INVALID_ARG, "refine set too large");
     const int32_t n_rng = (int32_t)n_rng64;
     SS_HIP_TRY(ctx->ranges.ensure((size_t)n_obj * n_rng * 16), "workspace");
-    SS_HIP_TRY(launch_plan(logits, obj_status, (const int64_t *)ctx->bin_k.p, (int)n_obj, top_k,
-                           margin, chunk, n_rng, (int64_t *)ctx->ranges.p, stream),
+    SS_HIP_TRY(launch_plan(logits, scores, gamma, obj_status, cat->offsets, full_below,
+                           (const int64_t *)ctx->bin_k.p, (int)n_obj, top_k, margin, chunk,
+                           n_rng, (int64_t *)ctx->ranges.p, stream),
                "refine planner");
     return trials(ctx, P, method, cat, grid, prm, nullptr, nullptr, true, obj_status, stream,
                   best_idx, best_period, best_power, chunk, n_rng,
                   (const int64_t *)ctx->ranges.p);
 }
 
-int check_learned(const ss_catalog *cat, int top_k, int margin) {
+// Cheap exact-grid scores of every log bin into ctx->scores (after prep).
+int bin_scores(ss_ctx *ctx, const ss_catalog *cat, const ss_grid *grid, int32_t *obj_status,
+               hipStream_t stream, float *out) {
+    int rc = upload_bin_table(ctx, grid);
+    if (rc != SS_OK) return rc;
+    ScoreArgs A{};
+    A.n_obj = (int)cat->n_obj;
+    A.offsets = cat->offsets;
+    A.tt = (const double *)ctx->tt.p;
+    A.w = (const double *)ctx->w.p;
+    A.yc = (const double *)ctx->yc.p;
+    A.chi0 = (const double *)ctx->chi0.p;
+    A.status = obj_status;
+    A.bin_k = (const int64_t *)ctx->bin_k.p;
+    A.fmin = grid->f_min;
+    A.df = (grid->f_max - grid->f_min) / (double)grid->n_freq;
+    A.n_freq = grid->n_freq;
+    A.scores = out;
+    SS_HIP_TRY(launch_bin_scores(A, ctx->n_cu, stream), "bin score kernel");
+    return SS_OK;
+}
+
+int check_learned(const ss_catalog *cat, int top_k, int margin, int full_below = 0) {
+    if (full_below < 0) return fail(SS_ERR_INVALID_ARG, "full_below must be >= 0");
     if (cat->n_obj > 0 && cat->n_obj > INT32_MAX / kEncBins)
         return fail(SS_ERR_INVALID_ARG, "n_obj too large for the encoder");
     if (top_k < 1 || top_k > kEncBins) return fail(SS_ERR_INVALID_ARG, "top_k must be in [1, 1024]");
@@ -449,7 +475,7 @@ void ss_ctx_destroy(ss_ctx *ctx) {
     ctx->chi0.release();
     ctx->sw.release();
     for (DevBuf *b : {&ctx->emb, &ctx->act, &ctx->logits, &ctx->dlog, &ctx->loss_o, &ctx->dE,
-                      &ctx->partial, &ctx->ranges, &ctx->bin_k})
+                      &ctx->partial, &ctx->ranges, &ctx->bin_k, &ctx->scores})
         b->release();
     ctx->objs.release();
     ctx->part_p.release();
@@ -631,11 +657,12 @@ int ss_adam_step(float *params, const float *grad, float *m, float *v, int64_t n
 
 int ss_refine_best_period(ss_ctx *ctx, int32_t method, const ss_catalog *cat,
                           const ss_grid *grid, const ss_params *params, const float *logits,
-                          int32_t top_k, int32_t margin, int64_t *best_idx, double *best_period,
-                          double *best_power, int32_t *obj_status, void *stream) {
+                          int32_t top_k, int32_t margin, int32_t full_below, int64_t *best_idx,
+                          double *best_period, double *best_power, int32_t *obj_status,
+                          void *stream) {
     int rc = check_common(ctx, cat, grid, params);
     if (rc != SS_OK) return rc;
-    rc = check_learned(cat, top_k, margin);
+    rc = check_learned(cat, top_k, margin, full_below);
     if (rc != SS_OK) return rc;
     if (method != SS_METHOD_SS && method != SS_METHOD_SSSP)
         return fail(SS_ERR_INVALID_ARG, "method must be SS_METHOD_SS or SS_METHOD_SSSP");
@@ -646,31 +673,68 @@ int ss_refine_best_period(ss_ctx *ctx, int32_t method, const ss_catalog *cat,
     Plan P;
     rc = prepare(ctx, method, cat, params, obj_status, s, P);
     if (rc != SS_OK) return rc;
-    return refine(ctx, P, method, cat, grid, params, logits, top_k, margin, obj_status, s,
-                  best_idx, best_period, best_power);
+    return refine(ctx, P, method, cat, grid, params, logits, nullptr, 0.0f, top_k, margin,
+                  full_below, obj_status, s, best_idx, best_period, best_power);
 }
 
 int ss_learned_best_period(ss_ctx *ctx, int32_t method, const ss_catalog *cat,
                            const ss_grid *grid, const ss_params *params, const float *enc_params,
-                           int32_t top_k, int32_t margin, int64_t *best_idx, double *best_period,
-                           double *best_power, int32_t *obj_status, void *stream) {
+                           float gamma, int32_t top_k, int32_t margin, int32_t full_below,
+                           int64_t *best_idx, double *best_period, double *best_power,
+                           int32_t *obj_status, void *stream) {
     int rc = check_common(ctx, cat, grid, params);
     if (rc != SS_OK) return rc;
-    rc = check_learned(cat, top_k, margin);
+    rc = check_learned(cat, top_k, margin, full_below);
     if (rc != SS_OK) return rc;
     if (method != SS_METHOD_SS && method != SS_METHOD_SSSP)
         return fail(SS_ERR_INVALID_ARG, "method must be SS_METHOD_SS or SS_METHOD_SSSP");
-    if (cat->n_obj > 0 && (!enc_params || !best_idx || !best_period || !best_power || !obj_status))
+    if (!std::isfinite(gamma) || gamma < 0.0f)
+        return fail(SS_ERR_INVALID_ARG, "gamma must be finite and >= 0");
+    if (!enc_params && gamma == 0.0f)
+        return fail(SS_ERR_INVALID_ARG, "no proposal: enc_params is null and gamma is 0");
+    if (cat->n_obj > 0 && (!best_idx || !best_period || !best_power || !obj_status))
         return fail(SS_ERR_INVALID_ARG, "null argument");
     if (cat->n_obj == 0) return SS_OK;
     const hipStream_t s = (hipStream_t)stream;
+    const int64_t n_obj = cat->n_obj;
     Plan P;
-    EncArgs A;
-    rc = encode(ctx, method, cat, grid, params, enc_params, obj_status, s, nullptr, nullptr, false,
-                P, A);
+    const float *logits = nullptr;
+    if (enc_params) {
+        EncArgs A;
+        rc = encode(ctx, method, cat, grid, params, enc_params, obj_status, s, nullptr, nullptr,
+                    false, P, A);
+        if (rc != SS_OK) return rc;
+        logits = (const float *)ctx->logits.p;
+    } else {
+        rc = prepare(ctx, method, cat, params, obj_status, s, P);
+        if (rc != SS_OK) return rc;
+    }
+    const float *scores = nullptr;
+    if (gamma > 0.0f) {
+        SS_HIP_TRY(ctx->scores.ensure((size_t)n_obj * kEncBins * 4), "workspace");
+        rc = bin_scores(ctx, cat, grid, obj_status, s, (float *)ctx->scores.p);
+        if (rc != SS_OK) return rc;
+        scores = (const float *)ctx->scores.p;
+    }
+    return refine(ctx, P, method, cat, grid, params, logits, scores, gamma, top_k, margin,
+                  full_below, obj_status, s, best_idx, best_period, best_power);
+}
+
+int ss_bin_scores(ss_ctx *ctx, const ss_catalog *cat, const ss_grid *grid, float *scores,
+                  int32_t *obj_status, void *stream) {
+    ss_params prm;
+    ss_params_default(&prm);
+    int rc = check_common(ctx, cat, grid, &prm);
     if (rc != SS_OK) return rc;
-    return refine(ctx, P, method, cat, grid, params, (const float *)ctx->logits.p, top_k, margin,
-                  obj_status, s, best_idx, best_period, best_power);
+    rc = check_learned(cat, 1, 0);
+    if (rc != SS_OK) return rc;
+    if (cat->n_obj > 0 && (!scores || !obj_status)) return fail(SS_ERR_INVALID_ARG, "null argument");
+    if (cat->n_obj == 0) return SS_OK;
+    const hipStream_t s = (hipStream_t)stream;
+    Plan P;
+    rc = prepare(ctx, SS_METHOD_SS, cat, &prm, obj_status, s, P);
+    if (rc != SS_OK) return rc;
+    return bin_scores(ctx, cat, grid, obj_status, s, scores);
 }
 
 int ss_bin_table(const ss_grid *grid, int64_t *first_k) {
@@ -688,6 +752,6 @@ int ss_enc_num_params(void) { return kEncParams; }
 
 const char *ss_last_error(void) { return g_last_error.c_str(); }
 
-int ss_version(void) { return 110; }
+int ss_version(void) { return 120; }
 
 }  // extern "C"

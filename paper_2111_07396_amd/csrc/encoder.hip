@@ -504,14 +504,19 @@ __global__ __launch_bounds__(256) void adam_kernel(float *__restrict__ p,
     p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
-// Refine planning, one wavefront per object: the top_k largest logits
-// (lowest bin first among equal values), each widened by `margin` bins on
-// both sides, merged into runs of consecutive bins, and each run turned into
-// fine-grid index ranges [bin_k[first], bin_k[last + 1]) cut into pieces of
-// at most `chunk` frequencies.  Writes n_rng ranges per object (unused
-// entries empty).
+// Refine planning, one wavefront per object: the top_k largest bin values
+// v_b = logit_b + gamma * score_b (either term absent when its pointer is
+// null; NaN ranks lowest; lowest bin first among equal values), each widened
+// by `margin` bins on both sides, merged into runs of consecutive bins, and
+// each run turned into fine-grid index ranges [bin_k[first], bin_k[last + 1])
+// cut into pieces of at most `chunk` frequencies.  Objects with fewer than
+// full_below points get the whole grid instead.  Writes n_rng ranges per
+// object (unused entries empty).
 __global__ __launch_bounds__(256) void plan_kernel(const float *__restrict__ logits,
+                                                   const float *__restrict__ scores, float gamma,
                                                    const int32_t *__restrict__ status,
+                                                   const int64_t *__restrict__ offsets,
+                                                   int full_below,
                                                    const int64_t *__restrict__ bin_k, int n_obj,
                                                    int top_k, int margin, int chunk, int n_rng,
                                                    int64_t *__restrict__ ranges) {
@@ -522,9 +527,13 @@ __global__ __launch_bounds__(256) void plan_kernel(const float *__restrict__ log
     constexpr int PER = NB / kWave;  // bins b = lane * PER + j
     float z[PER];
     uint32_t sel = 0u;  // bit j: bin lane * PER + j selected (after widening)
-    if (status[o] == 0) {
+    const bool whole = status[o] == 0 && offsets[o + 1] - offsets[o] < (int64_t)full_below;
+    if (whole) sel = 0xffffu;
+    if (status[o] == 0 && !whole) {
         for (int j = 0; j < PER; ++j) {
-            const float v = logits[(int64_t)o * NB + lane * PER + j];
+            const int64_t q = (int64_t)o * NB + lane * PER + j;
+            float v = logits ? logits[q] : 0.0f;
+            if (scores) v = fmaf(gamma, scores[q], v);
             z[j] = __builtin_isnan(v) ? -__builtin_inff() : v;
         }
         uint32_t taken = 0u;
@@ -663,12 +672,14 @@ hipError_t launch_adam(float *p, const float *g, float *m, float *v, int64_t n, 
     return hipGetLastError();
 }
 
-hipError_t launch_plan(const float *logits, const int32_t *status, const int64_t *bin_k,
-                       int n_obj, int top_k, int margin, int chunk, int n_rng, int64_t *ranges,
-                       hipStream_t s) {
+hipError_t launch_plan(const float *logits, const float *scores, float gamma,
+                       const int32_t *status, const int64_t *offsets, int full_below,
+                       const int64_t *bin_k, int n_obj, int top_k, int margin, int chunk,
+                       int n_rng, int64_t *ranges, hipStream_t s) {
     if (n_obj <= 0) return hipSuccess;
     hipLaunchKernelGGL(plan_kernel, dim3((unsigned)((n_obj + 3) / 4)), dim3(256), 0, s, logits,
-                       status, bin_k, n_obj, top_k, margin, chunk, n_rng, ranges);
+                       scores, gamma, status, offsets, full_below, bin_k, n_obj, top_k, margin,
+                       chunk, n_rng, ranges);
     return hipGetLastError();
 }
 

@@ -144,8 +144,29 @@ hipError_t launch_train_tail(const EncArgs &A, const float *logits, const int32_
                              int n_waves, hipStream_t s);
 hipError_t launch_adam(float *p, const float *g, float *m, float *v, int64_t n, float lr,
                        float b1, float b2, float eps, float c1, float c2, hipStream_t s);
-hipError_t launch_plan(const float *logits, const int32_t *status, const int64_t *bin_k,
-                       int n_obj, int top_k, int margin, int chunk, int n_rng, int64_t *ranges,
-                       hipStream_t s);
+hipError_t launch_plan(const float *logits, const float *scores, float gamma,
+                       const int32_t *status, const int64_t *offsets, int full_below,
+                       const int64_t *bin_k, int n_obj, int top_k, int margin, int chunk,
+                       int n_rng, int64_t *ranges, hipStream_t s);
+
+// Cheap exact-grid proposal score: for every grid frequency the fraction of
+// chi0 explained by a phase-binned (piecewise constant) model with
+// B = clamp(n / 5, 4, 32) equal phase bins, max-pooled into the 1024 log
+// bins of the grid (scores [n_obj][1024], zero for bins without a grid
+// frequency and for objects with a nonzero status).
+struct ScoreArgs {
+    int n_obj;
+    const int64_t *offsets;
+    const double *tt;     // prepped
+    const double *w, *yc;
+    const double *chi0;
+    const int32_t *status;
+    const int64_t *bin_k;  // 1025 first indices of the log bins
+    double fmin, df;
+    int64_t n_freq;
+    float *scores;
+};
+constexpr int kScoreMaxBins = 32;
+hipError_t launch_bin_scores(const ScoreArgs &A, int n_cu, hipStream_t s);
 
 }  // namespace ssg

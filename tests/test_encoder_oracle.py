@@ -205,3 +205,59 @@ def test_refine_contains_full_best():
     for o in range(3):
         assert bi[o] == int(np.nanargmax(pg[o]))
         assert bp[o] == pg[o, bi[o]]
+
+
+def test_bin_scores_closed_forms():
+    # a pure step at the first of B phase bins, sampled on an exact grid: at the
+    # generating frequency the binned model explains everything (score 1)
+    n, B = 40, 8
+    tau = 2.0 ** -5
+    t = np.arange(n) * tau                      # phases j/40 at f = 1/(n tau) (exact)
+    y = np.where(np.arange(n) % n < n // B, 1.0, 0.0) + 10.0
+    e = np.ones(n)
+    f0 = 1.0 / (n * tau)
+    grid = (f0 / 2, f0 * 2, 3 * 512)            # f0 is grid index 512 (exact)
+    assert ref.grid_f(*grid, 512) == f0
+    s = ref.bin_scores(t, y, e, grid)
+    tab = ref.bin_table(*grid)
+    b0 = int(np.searchsorted(tab, 512, side="right") - 1)
+    assert s[b0] == pytest.approx(1.0, abs=1e-12)
+    assert np.all(s <= 1.0 + 1e-12) and np.all(s >= 0.0)
+    # bins without grid frequencies score 0
+    assert np.all(s[np.diff(tab) == 0] == 0.0)
+
+
+def test_bin_scores_constant_object_is_zero():
+    t = np.linspace(0, 10, 30)
+    assert np.all(ref.bin_scores(t, np.full(30, 5.0), np.ones(30), (0.1, 5.0, 200)) == 0.0)
+
+
+def test_bin_scores_brute_force_one_frequency():
+    rng = np.random.default_rng(4)
+    n = 57
+    t = np.sort(rng.uniform(0, 100, n))
+    y = rng.normal(size=n)
+    e = rng.uniform(0.5, 2.0, n)
+    grid = (0.1, 3.0, 50)
+    s = ref.bin_scores(t, y, e, grid)
+    tab = ref.bin_table(*grid)
+    # recompute every frequency's score by explicit loops and pool by hand
+    w = 1.0 / e ** 2
+    yb = np.sum(w * y) / np.sum(w)
+    chi0 = np.sum(w * (y - yb) ** 2)
+    B = 11
+    tt = t - t.min()
+    best = {}
+    for k in range(50):
+        f = 0.1 + k * (2.9 / 50)
+        Wb, Sb = [0.0] * B, [0.0] * B
+        for i in range(n):
+            q = tt[i] * f
+            jb = min(B - 1, int((q - np.floor(q)) * B))
+            Wb[jb] += w[i]
+            Sb[jb] += w[i] * (y[i] - yb)
+        sc = sum(Sb[j] ** 2 / Wb[j] for j in range(B) if Wb[j] > 0) / chi0
+        b = int(np.searchsorted(tab, k, side="right") - 1)
+        best[b] = max(best.get(b, 0.0), sc)
+    for b, v in best.items():
+        assert s[b] == pytest.approx(v, rel=1e-10)

@@ -148,8 +148,9 @@ def test_adam_step_matches_definition():
 
 
 @pytest.mark.parametrize("method", [oracle.SS, oracle.SSSP])
-@pytest.mark.parametrize("top_k,margin", [(16, 1), (3, 0), (40, 2)])
-def test_refine_matches_reference(ctx, method, top_k, margin):
+@pytest.mark.parametrize("top_k,margin,full_below", [(16, 1, 0), (3, 0, 0), (40, 2, 0),
+                                                     (4, 1, 120)])
+def test_refine_matches_reference(ctx, method, top_k, margin, full_below):
     import torch
     cat = synth.make_catalog(31, 12, (40, 260), 1000.0, (0.2, 10.0), 0.05)
     cat.y[cat.offsets[4]:cat.offsets[5]] = 15.0  # object 4: constant magnitudes
@@ -157,10 +158,10 @@ def test_refine_matches_reference(ctx, method, top_k, margin):
     logits = np.random.default_rng(7).normal(size=(cat.n_obj, ref.BINS)).astype(np.float32)
     logits[1, 100:110] = 5.0  # equal logits: lower bins first
     bi_o, bp_o = ref.refine_best(method, cat.offsets, cat.t, cat.y, cat.e, grid,
-                                 logits.astype(np.float64), top_k, margin)
+                                 logits.astype(np.float64), top_k, margin, full_below=full_below)
     dc = ssg.DeviceCatalog.from_numpy(cat.offsets, cat.t, cat.y, cat.e)
     lt = torch.tensor(logits, device="cuda")
-    bi, bp, bw, st = ctx.refine_best_period(method, dc, grid, lt, top_k, margin)
+    bi, bp, bw, st = ctx.refine_best_period(method, dc, grid, lt, top_k, margin, full_below)
     torch.cuda.synchronize()
     bi, bw, st = bi.cpu().numpy(), bw.cpu().numpy(), st.cpu().numpy()
     assert st[4] == ssg.OBJ_CONST_MAG and bi[4] == -1 and np.isnan(bw[4])
@@ -173,6 +174,8 @@ def test_refine_matches_reference(ctx, method, top_k, margin):
             continue
         if bi[o] != bi_o[o]:
             ks = ref.refine_set(logits[o].astype(np.float64), top_k, margin, table)
+            if cat.offsets[o + 1] - cat.offsets[o] < full_below:
+                ks = np.arange(grid[2])
             a, b = cat.offsets[o], cat.offsets[o + 1]
             pg, _ = oracle.periodogram(method, np.array([0, b - a]), cat.t[a:b], cat.y[a:b],
                                        cat.e[a:b], *grid, ks=ks)
@@ -203,7 +206,39 @@ def test_learned_call_equals_forward_then_refine(ctx):
     dc = ssg.DeviceCatalog.from_numpy(cat.offsets, cat.t, cat.y, cat.e)
     _, logits, _ = ctx.enc_forward(dc, grid, pt)
     a = ctx.refine_best_period(0, dc, grid, logits, 16, 1)
-    b = ctx.learned_best_period(0, dc, grid, pt, 16, 1)
+    b = ctx.learned_best_period(0, dc, grid, pt, 0.0, 16, 1)
     torch.cuda.synchronize()
     for x, y in zip(a, b):
         assert torch.equal(x, y)
+
+
+def test_bin_scores_match_reference(ctx):
+    import torch
+    cat = synth.make_catalog(34, 10, (20, 400), 1000.0, (0.2, 10.0), 0.05)
+    cat.e[cat.offsets[3]] = 0.0  # object 3: bad error bar
+    grid = (0.1, 10.0, 3000)
+    dc = ssg.DeviceCatalog.from_numpy(cat.offsets, cat.t, cat.y, cat.e)
+    sc, st = ctx.bin_scores(dc, grid)
+    torch.cuda.synchronize()
+    sc = sc.cpu().numpy().astype(np.float64)
+    assert st.cpu().numpy()[3] == ssg.OBJ_BAD_ERR
+    for o in range(cat.n_obj):
+        a, b = cat.offsets[o], cat.offsets[o + 1]
+        r = ref.bin_scores(cat.t[a:b], cat.y[a:b], cat.e[a:b], grid)
+        # FP32 sums of at most 400 terms: relative error well under 1e-4
+        np.testing.assert_allclose(sc[o], r, rtol=1e-4, atol=2e-6, err_msg=str(o))
+
+
+def test_score_proposal_equals_refine_on_scores(ctx):
+    """gamma x scores with no encoder selects exactly the top bins of the scores."""
+    import torch
+    cat = synth.make_catalog(35, 16, (30, 300), 1000.0, (0.2, 10.0), 0.05)
+    grid = (0.1, 10.0, 4000)
+    dc = ssg.DeviceCatalog.from_numpy(cat.offsets, cat.t, cat.y, cat.e)
+    sc, _ = ctx.bin_scores(dc, grid)
+    for method in (0, 1):
+        a = ctx.refine_best_period(method, dc, grid, sc, 8, 1)
+        b = ctx.learned_best_period(method, dc, grid, None, 1.0, 8, 1)
+        torch.cuda.synchronize()
+        for x, y in zip(a, b):
+            assert torch.equal(x, y)
