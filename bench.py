@@ -22,7 +22,6 @@ single dense object) and the learned-proposal comparison.
 from __future__ import annotations
 
 import argparse
-import glob
 import hashlib
 import json
 import os
@@ -43,10 +42,16 @@ ENCODER_WEIGHTS = os.path.join(ROOT, "paper_2111_07396_amd", "weights", "encoder
 
 
 def _src_hash() -> str:
+    """Hash of the sources the trial kernel is built from (its own file, the
+    arithmetic and wavefront helpers, and the launch structures that precede
+    the learned-proposal declarations in the internal header)."""
+    csrc = os.path.join(ROOT, "paper_2111_07396_amd", "csrc")
     h = hashlib.sha256()
-    for p in sorted(glob.glob(os.path.join(ROOT, "paper_2111_07396_amd", "csrc", "*"))):
-        with open(p, "rb") as f:
+    for name in ("trial.hip", "numeric.hpp", "wave.hpp"):
+        with open(os.path.join(csrc, name), "rb") as f:
             h.update(f.read())
+    with open(os.path.join(csrc, "ssgpu_internal.hpp"), "rb") as f:
+        h.update(f.read().split(b"// ---- learned frequency proposal")[0])
     return h.hexdigest()[:16]
 
 

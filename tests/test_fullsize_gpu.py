@@ -1,0 +1,82 @@
+"""Parity at the benchmark's full sizes, in the launch configuration the
+benchmark times (ss_best_period over whole catalogs), checked on outputs the
+oracle can compute one by one: for sampled objects the oracle's full
+periodogram (best index under the usual tie band, best power within
+1e-4 (1 - P)); for the dense single object the oracle's power at sampled
+frequencies and at the GPU's best frequency, plus the fact that no sampled
+frequency beats the GPU's best."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2111_07396_amd as ssg
+from paper_2111_07396_amd import synth
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = ssg.Context(0)
+    yield c
+    c.close()
+
+
+def _check_objects(cat, grid, bi, bw, method, objs, band=TOL):
+    for o in objs:
+        sub = cat.subset(np.array([o]))
+        po, so = oracle.periodogram(method, sub.offsets, sub.t, sub.y, sub.e, *grid)
+        assert so[0] == 0
+        ko = oracle.best(po[0])
+        assert abs(bw[o] - po[0, ko]) <= band * (1.0 - po[0, ko]) + 1e-12, o
+        if bi[o] != ko:
+            assert po[0, ko] - po[0, bi[o]] <= band * (1.0 - po[0, ko]), (o, bi[o], ko)
+
+
+@pytest.mark.parametrize("method", [oracle.SS, oracle.SSSP])
+def test_n200_catalog_full_size(ctx, method):
+    import torch
+    cat, grid = synth.catalog_n200()
+    dc = ssg.DeviceCatalog.from_numpy(cat.offsets, cat.t, cat.y, cat.e)
+    bi, bp, bw, st = ctx.ss_best_period(method, dc, grid)
+    torch.cuda.synchronize()
+    bi, bw, st = bi.cpu().numpy(), bw.cpu().numpy(), st.cpu().numpy()
+    assert (st == 0).all() and (bi >= 0).all()
+    objs = np.random.default_rng(100 + method).choice(cat.n_obj, 4, replace=False)
+    _check_objects(cat, grid, bi, bw, method, objs)
+
+
+def test_uneven_catalog_full_size_fp32c(ctx):
+    import torch
+    cat, grid = synth.catalog_uneven()
+    dc = ssg.DeviceCatalog.from_numpy(cat.offsets, cat.t, cat.y, cat.e)
+    prm = ssg.Params(precision=ssg.SS_FP32C)
+    bi, bp, bw, st = ctx.ss_best_period(oracle.SS, dc, grid, prm)
+    torch.cuda.synchronize()
+    bi, bw, st = bi.cpu().numpy(), bw.cpu().numpy(), st.cpu().numpy()
+    assert (st == 0).all()
+    lens = np.diff(cat.offsets)
+    objs = [int(np.argmin(lens)), int(np.argmax(lens))] + \
+        list(np.random.default_rng(7).choice(cat.n_obj, 2, replace=False))
+    # the FP32c band of the FP32c parity tests
+    _check_objects(cat, grid, bi, bw, oracle.SS, objs, band=1e-3)
+
+
+@pytest.mark.parametrize("method", [oracle.SS, oracle.SSSP])
+def test_dense_object_full_size(ctx, method):
+    import torch
+    cat, grid = synth.single_dense()
+    dc = ssg.DeviceCatalog.from_numpy(cat.offsets, cat.t, cat.y, cat.e)
+    fn = ctx.ss_periodogram if method == oracle.SS else ctx.sssp_periodogram
+    pg, st = fn(dc, grid)
+    best = ctx.ss_best_period(method, dc, grid)
+    torch.cuda.synchronize()
+    pg = pg.cpu().numpy()[0]
+    kb = int(best[0].cpu().numpy()[0])
+    assert kb == int(np.argmax(pg))
+    ks = np.unique(np.concatenate([np.random.default_rng(3).integers(0, grid[2], 60), [kb]]))
+    po, so = oracle.periodogram(method, cat.offsets, cat.t, cat.y, cat.e, *grid, ks=ks)
+    d = np.abs(pg[ks] - po[0])
+    assert np.all(d <= TOL * (1.0 - po[0]) + 1e-12), float(np.max(d / (1 - po[0])))
+    assert np.max(po[0]) <= po[0][np.searchsorted(ks, kb)] + TOL * (1 - po[0].max())
