@@ -87,6 +87,45 @@ def _best_rates(ctx, dc, grid, params, steps, methods):
     return out
 
 
+# BF16 dense matrix-core peak of MI355X (TFLOP/s).
+PEAK_BF16_TFLOPS = 2500.0
+
+
+def _proposal_kernels(ctx, ssg, dc, grid, cat):
+    """Rates of the proposal's own kernels on the mixed-stream sample: the
+    set encoder forward (per-point layers on the BF16 matrix cores) and one
+    training gradient, and the exact-grid bin scores."""
+    import numpy as np
+    import torch
+    from paper_2111_07396_amd import learn
+    n_pts = int(cat.offsets[-1])
+    w = torch.tensor(learn.init_params(0), dtype=torch.float32, device="cuda")
+    lab = torch.zeros(dc.n_obj, dtype=torch.int32, device="cuda")
+
+    def timed(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    t_fwd = timed(lambda: ctx.enc_forward(dc, grid, w))
+    t_grad = timed(lambda: ctx.enc_train_grad(dc, grid, w, lab))
+    t_sc = timed(lambda: ctx.bin_scores(dc, grid))
+    # matrix-core work: 80x64 + 64x128 MACs per point (32-point tiles, padding counted as
+    # algorithmic zero work: only real points); the head's 128x1024 per object is FP32 VALU
+    mac_pts = (80 * 64 + 64 * 128) * n_pts
+    tflops = 2.0 * mac_pts / t_fwd / 1e12
+    return {"encoder_forward_ms": t_fwd * 1e3, "encoder_obj_per_s": dc.n_obj / t_fwd,
+            "encoder_mfma_tflops": tflops, "encoder_frac_bf16_peak": tflops / PEAK_BF16_TFLOPS,
+            "encoder_train_grad_ms": t_grad * 1e3,
+            "bin_scores_ms": t_sc * 1e3,
+            "bin_scores_trials_per_s": dc.n_obj * int(grid[2]) / t_sc,
+            "points": n_pts, "objects": dc.n_obj}
+
+
 def _extras(ctx, ssg, synth, args):
     """Measurements outside the timed region (each run once after a warm-up)."""
     import numpy as np
@@ -157,6 +196,7 @@ def _extras(ctx, ssg, synth, args):
         rl["encoder_only"] = learn.compare(ctx, dc5, grid5, w, 0.0, pol["top_k"], pol["margin"],
                                            pol["full_below"], full=full5)
     ex["proposal_vs_full"] = rl
+    ex["proposal_kernels"] = _proposal_kernels(ctx, ssg, dc5, grid5, cat5)
     return ex
 
 
