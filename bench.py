@@ -179,8 +179,16 @@ def _extras(ctx, ssg, synth, args):
         r = _best_rates(ctx, dc3, grid3, ssg.Params(precision=pv), 1, both)
         ex["single_dense"][pn] = {names[m]: {"ms": r[m]["wall_ms"], "trials_per_s":
                                              r[m]["trials_per_s"]} for m in both}
-    # proposal + exact refine against the full grid on a mixed-stream sample
+    ex.update(_proposal(ctx, ssg, synth, args))
+    return ex
+
+
+def _proposal(ctx, ssg, synth, args):
+    """Proposal + exact refine against the full grid on a mixed-stream sample."""
+    import numpy as np
+    import torch
     from paper_2111_07396_amd import learn
+    ex = {}
     cat5, grid5 = synth.catalog_mixed(n_obj=args.learned_objects)
     dc5 = ssg.DeviceCatalog.from_numpy(cat5.offsets, cat5.t, cat5.y, cat5.e)
     full5 = ctx.ss_best_period(ssg.SS_METHOD_SS, dc5, grid5)
@@ -211,6 +219,8 @@ def main() -> int:
     ap.add_argument("--learned-objects", type=int, default=2000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--proposal-only", action="store_true",
+                    help="measure only the proposal + refine comparison and print it")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -224,6 +234,11 @@ def main() -> int:
     import paper_2111_07396_amd as ssg
     from paper_2111_07396_amd import synth
 
+    if args.proposal_only:
+        ctx = ssg.Context(0)
+        print(json.dumps(_proposal(ctx, ssg, synth, args)), flush=True)
+        ctx.close()
+        return 0
     cat, grid = synth.catalog_n200(n_obj=args.n_obj)
     n_obj, n_freq = cat.n_obj, int(grid[2])
     npts = int(cat.lengths()[0])
