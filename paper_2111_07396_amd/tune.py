@@ -15,7 +15,7 @@ import os
 
 import numpy as np
 
-from . import DeviceCatalog, Params, SS_METHOD_SS, shapes
+from . import OBJ_TOO_LONG, DeviceCatalog, Params, SSError, SS_METHOD_SS, shapes
 
 # Length ranges tuned separately: (lo, hi] of points per object.
 RANGES = ((0, 64), (64, 128), (128, 192), (192, 256), (256, 384), (384, 512), (512, 1024),
@@ -79,7 +79,11 @@ def tune(ctx, offsets, t, y, e, grid, params: Params | None = None, method=SS_ME
                     torch.cuda.synchronize()
                     out = ctx.ss_best_period(method, dc, g_s, params, out=out)
                     ms, _ = ctx.trial_kernel_ms()
-                except Exception:  # shape does not fit (LDS) at this span
+                except SSError:  # shape rejected for this range
+                    continue
+                # a shape whose LDS does not hold the spans marks its objects too long
+                # and returns at once: never a candidate
+                if bool((out[3] == OBJ_TOO_LONG).any()):
                     continue
                 rate = idx.size * nf_s / (ms * 1e-3)
                 if verbose:
