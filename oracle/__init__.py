@@ -19,7 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libss_oracle.so")
 
 STATUS_OK, STATUS_TOO_FEW, STATUS_BAD_ERR, STATUS_NONFINITE, STATUS_CONST_MAG = 0, 1, 2, 3, 4
-SS, SSSP = 0, 1
+SS, SSSP, SSSP2 = 0, 1, 2
 DEFAULT_SPANS = (0.05, 0.2, 0.5)
 
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -61,6 +61,9 @@ def _load():
     lib.ora_sssp.restype = ctypes.c_double
     lib.ora_sssp.argtypes = [ctypes.c_int, _dp, _dp, _dp, ctypes.c_int, _dp, ctypes.c_int,
                              ctypes.c_double, _dp, _dp, ctypes.POINTER(ctypes.c_int)]
+    lib.ora_sssp2.restype = ctypes.c_double
+    lib.ora_sssp2.argtypes = [ctypes.c_int, _dp, _dp, _dp, ctypes.c_int, _dp, ctypes.c_double,
+                              ctypes.c_double]
     lib.ora_trial.restype = ctypes.c_double
     lib.ora_trial.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, _dp, ctypes.c_double,
                               ctypes.c_double, ctypes.c_int, _dp, ctypes.c_double, ctypes.c_double]
@@ -168,6 +171,17 @@ def sssp(x, y, w, spans=DEFAULT_SPANS, fixed_span=0.0, periodic=True):
     chi2 = _load().ora_sssp(x.size, xp, yp, wp, 2 if periodic else 1, spp, K, fixed_span, rp, tp,
                             ctypes.byref(kb))
     return float(chi2), rss, tr, kb.value
+
+
+def sssp2(x, y, w, spans=DEFAULT_SPANS, alpha=9.0, fixed_span=0.0, periodic=True):
+    """chi^2 of the second single-pass reading (per-point span choice by the
+    un-smoothed GV residual, bass, blend)."""
+    x, xp = _d(x)
+    y, yp = _d(y)
+    w, wp = _d(w)
+    sp_, spp = _d(np.asarray(spans, dtype=np.float64))
+    return float(_load().ora_sssp2(x.size, xp, yp, wp, 2 if periodic else 1, spp, alpha,
+                                   fixed_span))
 
 
 def trial(method, tt, y, w, chi0, f, spans=DEFAULT_SPANS, alpha=9.0, fixed_span=0.0,

@@ -33,6 +33,12 @@
  *                   sweep over K candidate spans scored by generalized
  *                   cross-validation GCV_k = RSS_k / (1 - TR_k/n)^2, the first
  *                   minimum wins, chi^2 = RSS_k*.
+ *   ora_sssp2       A second reading of the Sec. 3 variant: the same single
+ *                   sweep (smooths s_k and traces TR_k of the K = 3 spans),
+ *                   then a span choice per point by the un-smoothed
+ *                   generalized-validation residual |y - s_k| / (1 - TR_k/n)
+ *                   with Listing 1's scan, bass enhancement, clip and blend
+ *                   (its residual, span and final smooths left out).
  *   ora_trial       fold -> sort -> smoother -> chi^2 -> P = 1 - chi^2/chi0
  *                   (Alg. 1 computePgram; formula read as stated).
  *   ora_periodogram Alg. 1 over a catalog of objects (Sec. 4.3 batch mode).
@@ -61,6 +67,7 @@
 
 #define ORA_METHOD_SS 0
 #define ORA_METHOD_SSSP 1
+#define ORA_METHOD_SSSP2 2
 
 /* ------------------------------------------------------------------ prep */
 
@@ -413,6 +420,68 @@ double ora_sssp(int n, const double *x, const double *y, const double *w, int ip
     return chi2;
 }
 
+/* Second reading of the Sec. 3 variant (see the header).  alpha as in
+ * Listing 1; with a fixed span it is the fixed-span smooth. */
+double ora_sssp2(int n, const double *x, const double *y, const double *w, int iper,
+                 const double *spans, double alpha, double fixed_span)
+{
+    double *buf = (double *)malloc((size_t)n * 6 * sizeof(double));
+    double *s[3] = {buf, buf + n, buf + 2 * n};
+    double *r = buf + 3 * n, *lev = buf + 4 * n, *smo = buf + 5 * n;
+    double chi2 = 0.0;
+    if (degenerate_fill(n, x, y, w, smo)) {
+        for (int j = 0; j < n; ++j) chi2 += w[j] * (y[j] - smo[j]) * (y[j] - smo[j]);
+        free(buf);
+        return chi2;
+    }
+    double vsmlsq = listing_vsmlsq(n, x);
+    int per = listing_periodic(n, x, iper);
+    if (fixed_span > 0.0) {
+        ora_smooth(n, x, y, w, fixed_span, per, 1, vsmlsq, smo, r, lev);
+        for (int j = 0; j < n; ++j) chi2 += w[j] * (y[j] - smo[j]) * (y[j] - smo[j]);
+        free(buf);
+        return chi2;
+    }
+    double den[3];
+    int ok[3];
+    for (int k = 0; k < 3; ++k) {
+        ora_smooth(n, x, y, w, spans[k], per, 1, vsmlsq, s[k], r, lev);
+        double tr = 0.0;
+        for (int j = 0; j < n; ++j) tr += w[j] * lev[j];
+        ok[k] = tr < (double)n;
+        den[k] = 1.0 - tr / (double)n;
+    }
+    for (int j = 0; j < n; ++j) {
+        double e[3];
+        for (int k = 0; k < 3; ++k) e[k] = ok[k] ? fabs(y[j] - s[k][j]) / den[k] : INFINITY;
+        double resmin = 1e20, sel = 0.0;
+        for (int k = 0; k < 3; ++k) {
+            if (e[k] < resmin) {
+                resmin = e[k];
+                sel = spans[k];
+            }
+        }
+        if (alpha > 0.0 && alpha <= 10.0 && resmin < e[2] && resmin > 0.0) {
+            double tmp = resmin / e[2];
+            if (tmp < 1e-7) tmp = 1e-7;
+            sel += (spans[2] - sel) * pow(tmp, 10.0 - alpha);
+        }
+        if (sel <= spans[0]) sel = spans[0];
+        if (sel >= spans[2]) sel = spans[2];
+        double f = sel - spans[1], b;
+        if (f < 0.0) {
+            f = f / (spans[0] - spans[1]);
+            b = (1.0 - f) * s[1][j] + f * s[0][j];
+        } else {
+            f = f / (spans[2] - spans[1]);
+            b = (1.0 - f) * s[1][j] + f * s[2][j];
+        }
+        chi2 += w[j] * (y[j] - b) * (y[j] - b);
+    }
+    free(buf);
+    return chi2;
+}
+
 /* ------------------------------------------------------------------ one trial */
 
 /* One (object, frequency) trial: fold, stable sort, smoother, chi^2, P.
@@ -436,8 +505,10 @@ double ora_trial(int method, int n, const double *tt, const double *y, const dou
         ora_supsmu(n, xs, ys, ws, iper, spans, alpha, fixed_span, smo);
         chi2 = 0.0;
         for (int j = 0; j < n; ++j) chi2 += ws[j] * (ys[j] - smo[j]) * (ys[j] - smo[j]);
-    } else {
+    } else if (method == ORA_METHOD_SSSP) {
         chi2 = ora_sssp(n, xs, ys, ws, iper, spans, 3, fixed_span, NULL, NULL, NULL);
+    } else {
+        chi2 = ora_sssp2(n, xs, ys, ws, iper, spans, alpha, fixed_span);
     }
     free(perm);
     free(ph);

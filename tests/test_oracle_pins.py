@@ -186,6 +186,48 @@ def test_trial_sssp_closed_form():
     np.testing.assert_allclose(rss, [chi0 * (1 - d) ** 2 for d in D], rtol=1e-10)
 
 
+def _blend_gain(alpha, n=64):
+    # span choice from the per-point residual ratios c_k (the same for every
+    # point of the sinusoid), bass, clip, blend: the blend is B times y
+    m = [2 * oracle.halfwidth(n, s) + 1 for s in SPANS]
+    D = [bf.dirichlet_gain(mm, n) for mm in m]
+    c = [(1 - D[k]) / (1 - 1.0 / m[k]) for k in range(3)]
+    k = int(np.argmin(c))
+    span = SPANS[k]
+    if 0 < alpha <= 10 and c[k] < c[2]:
+        span += (SPANS[2] - span) * max(c[k] / c[2], 1e-7) ** (10 - alpha)
+    span = min(max(span, SPANS[0]), SPANS[2])
+    f = span - SPANS[1]
+    if f < 0:
+        f /= SPANS[0] - SPANS[1]
+        return (1 - f) * D[1] + f * D[0]
+    f /= SPANS[2] - SPANS[1]
+    return (1 - f) * D[1] + f * D[2]
+
+
+@pytest.mark.parametrize("alpha", [0.0, 3.5, 9.0, 10.0])
+def test_trial_sssp2_closed_form(alpha):
+    # second single-pass reading on the sinusoid: TR_k = n/m_k, so the
+    # un-smoothed residual |y - D_k y| / (1 - 1/m_k) is c_k |y| at every point;
+    # the choice, bass and blend are constant and the fit is B y (no final smooth)
+    t, y, e = _sinusoid_object()
+    st, tt, w, ybar, chi0 = oracle.prep(t, y, e)
+    p = oracle.trial(oracle.SSSP2, tt, y, w, chi0, 1.0, alpha=alpha)
+    assert abs(p - (1 - (1 - _blend_gain(alpha)) ** 2)) < 1e-12
+    # the Listing 1 driver is the same blend followed by the tweeter smooth
+    m0 = 2 * oracle.halfwidth(64, SPANS[0]) + 1
+    assert abs(_ss_closed_form(alpha) - (1 - (1 - bf.dirichlet_gain(m0, 64)
+                                              * _blend_gain(alpha)) ** 2)) < 1e-12
+
+
+def test_trial_sssp2_fixed_span_is_the_smooth():
+    t, y, e = _sinusoid_object()
+    st, tt, w, ybar, chi0 = oracle.prep(t, y, e)
+    for span in SPANS:
+        p = oracle.trial(oracle.SSSP2, tt, y, w, chi0, 1.0, fixed_span=span)
+        assert abs(p - oracle.trial(oracle.SS, tt, y, w, chi0, 1.0, fixed_span=span)) < 1e-12
+
+
 def test_supsmu_nonperiodic_line_is_fixed_point():
     rng = np.random.default_rng(2)
     n = 50
@@ -237,7 +279,7 @@ def _small_catalog(seed=4, n_obj=3):
     return offs, t, y, e
 
 
-@pytest.mark.parametrize("method", [oracle.SS, oracle.SSSP])
+@pytest.mark.parametrize("method", [oracle.SS, oracle.SSSP, oracle.SSSP2])
 def test_periodogram_invariances(method):
     offs, t, y, e = _small_catalog()
     grid = (0.2, 3.0, 40)
