@@ -59,9 +59,17 @@ extern "C" {
 #define SS_FP32C 1 /* FP32 arithmetic with compensated (two-float) window sums;
                       FP64 fold and chi^2/chi0 normalisation; periodogram is float */
 
-/* ---- method (ss_best_period) */
-#define SS_METHOD_SS 0   /* Listing 1: cross-validated variable-span smoother */
-#define SS_METHOD_SSSP 1 /* Sec. 3: single-pass generalized validation */
+/* ---- method (ss_best_period, ss_method_periodogram) */
+#define SS_METHOD_SS 0      /* Listing 1: cross-validated variable-span smoother */
+#define SS_METHOD_SSSP 1    /* Sec. 3: single-pass generalized validation, read as one
+                               sweep over the three spans with GCV_k = RSS_k / (1 -
+                               TR_k/n)^2 choosing one span per trial (first minimum),
+                               chi^2 = RSS of that span */
+#define SS_METHOD_SSSP_GV 2 /* Sec. 3, second reading: the same sweep, then a span per
+                               point by |y - s_k| / (1 - TR_k/n) (Listing 1's scan:
+                               strict <, from 1e20), bass enhancement against the
+                               largest span, clip and blend as in Listing 1, chi^2 of
+                               the blend (no residual, span or final smooth) */
 
 /* Largest light curve the library accepts (points per object). */
 #define SS_MAX_POINTS 4096
@@ -130,6 +138,12 @@ int ss_periodogram(ss_ctx *ctx, const ss_catalog *cat, const ss_grid *grid,
  * chi2 = its RSS.  params.alpha is ignored. */
 int sssp_periodogram(ss_ctx *ctx, const ss_catalog *cat, const ss_grid *grid,
                      const ss_params *params, void *pgram, int32_t *obj_status, void *stream);
+
+/* Periodogram of any method (SS_METHOD_*): as ss_periodogram, with the method
+ * chosen by `method` (alpha used by SS and SSSP_GV). */
+int ss_method_periodogram(ss_ctx *ctx, int32_t method, const ss_catalog *cat,
+                          const ss_grid *grid, const ss_params *params, void *pgram,
+                          int32_t *obj_status, void *stream);
 
 /* Best period per object without materialising the periodogram (Alg. 1
  * findPeriod): best_idx[o] = the lowest k attaining the largest P (NaN

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libssgpu.so")
 SS_OK = 0
 SS_ERR_INVALID_ARG, SS_ERR_HIP, SS_ERR_OOM, SS_ERR_UNSUPPORTED = -1, -2, -3, -4
 SS_FP64, SS_FP32C = 0, 1
-SS_METHOD_SS, SS_METHOD_SSSP = 0, 1
+SS_METHOD_SS, SS_METHOD_SSSP, SS_METHOD_SSSP_GV = 0, 1, 2
 OBJ_OK, OBJ_TOO_FEW, OBJ_BAD_ERR, OBJ_NONFINITE, OBJ_CONST_MAG = 0, 1, 2, 3, 4
 OBJ_TOO_LONG, OBJ_BAD_RANGE = 5, 6
 MAX_POINTS = 4096
@@ -30,7 +30,7 @@ EXPORTED = ("ss_params_default", "ss_ctx_create", "ss_ctx_destroy", "ss_periodog
             "ss_ctx_set_shape", "ss_ctx_set_tile", "ss_ctx_set_timing", "ss_ctx_trial_kernel_ms",
             "ss_last_error", "ss_version", "ss_bin_table", "ss_enc_num_params", "ss_enc_forward",
             "ss_enc_train_grad", "ss_adam_step", "ss_refine_best_period",
-            "ss_learned_best_period", "ss_bin_scores")
+            "ss_learned_best_period", "ss_bin_scores", "ss_method_periodogram")
 ENC_PARAMS = 145536
 ENC_BINS = 1024
 
@@ -93,6 +93,10 @@ def load_library(path: str = LIB_PATH):
         f.argtypes = [vp, ctypes.POINTER(_Catalog), ctypes.POINTER(_Grid), ctypes.POINTER(_Params),
                       vp, vp, vp]
         f.restype = ctypes.c_int
+    lib.ss_method_periodogram.argtypes = [vp, i32, ctypes.POINTER(_Catalog),
+                                          ctypes.POINTER(_Grid), ctypes.POINTER(_Params), vp,
+                                          vp, vp]
+    lib.ss_method_periodogram.restype = ctypes.c_int
     lib.ss_best_period.argtypes = [vp, i32, ctypes.POINTER(_Catalog), ctypes.POINTER(_Grid),
                                    ctypes.POINTER(_Params), vp, vp, vp, vp, vp]
     lib.ss_best_period.restype = ctypes.c_int
@@ -293,6 +297,13 @@ class Context:
         """P[o, k] of the single-pass generalized-validation variant (Sec. 3)."""
         return self._pgram(_lib.sssp_periodogram, cat, grid, params or Params(), out, status,
                            stream)
+
+    def method_periodogram(self, method, cat, grid, params=None, out=None, status=None,
+                           stream=None):
+        """P[o, k] of any method (SS_METHOD_SS, _SSSP or _SSSP_GV)."""
+        m = int(method)
+        return self._pgram(lambda *a: _lib.ss_method_periodogram(a[0], m, *a[1:]), cat, grid,
+                           params or Params(), out, status, stream)
 
     def ss_best_period(self, method, cat, grid, params=None, out=None, stream=None):
         """(best_idx int64, best_period f64, best_power f64, status int32) per object."""

@@ -511,13 +511,28 @@ int sssp_periodogram(ss_ctx *ctx, const ss_catalog *cat, const ss_grid *grid,
                nullptr, nullptr);
 }
 
+int ss_method_periodogram(ss_ctx *ctx, int32_t method, const ss_catalog *cat,
+                          const ss_grid *grid, const ss_params *params, void *pgram,
+                          int32_t *obj_status, void *stream) {
+    int rc = check_common(ctx, cat, grid, params);
+    if (rc != SS_OK) return rc;
+    if (method != SS_METHOD_SS && method != SS_METHOD_SSSP && method != SS_METHOD_SSSP_GV)
+        return fail(SS_ERR_INVALID_ARG, "method must be SS_METHOD_SS, _SSSP or _SSSP_GV");
+    if (cat->n_obj > 0 && (!pgram || !obj_status))
+        return fail(SS_ERR_INVALID_ARG, "null output pointer");
+    bool f64 = params->precision == SS_FP64;
+    return run(ctx, method, cat, grid, params, f64 ? (double *)pgram : nullptr,
+               f64 ? nullptr : (float *)pgram, false, obj_status, (hipStream_t)stream, nullptr,
+               nullptr, nullptr);
+}
+
 int ss_best_period(ss_ctx *ctx, int32_t method, const ss_catalog *cat, const ss_grid *grid,
                    const ss_params *params, int64_t *best_idx, double *best_period,
                    double *best_power, int32_t *obj_status, void *stream) {
     int rc = check_common(ctx, cat, grid, params);
     if (rc != SS_OK) return rc;
-    if (method != SS_METHOD_SS && method != SS_METHOD_SSSP)
-        return fail(SS_ERR_INVALID_ARG, "method must be SS_METHOD_SS or SS_METHOD_SSSP");
+    if (method != SS_METHOD_SS && method != SS_METHOD_SSSP && method != SS_METHOD_SSSP_GV)
+        return fail(SS_ERR_INVALID_ARG, "method must be SS_METHOD_SS, _SSSP or _SSSP_GV");
     if (cat->n_obj > 0 && (!best_idx || !best_period || !best_power || !obj_status))
         return fail(SS_ERR_INVALID_ARG, "null output pointer");
     return run(ctx, method, cat, grid, params, nullptr, nullptr, true, obj_status,
@@ -664,8 +679,8 @@ int ss_refine_best_period(ss_ctx *ctx, int32_t method, const ss_catalog *cat,
     if (rc != SS_OK) return rc;
     rc = check_learned(cat, top_k, margin, full_below);
     if (rc != SS_OK) return rc;
-    if (method != SS_METHOD_SS && method != SS_METHOD_SSSP)
-        return fail(SS_ERR_INVALID_ARG, "method must be SS_METHOD_SS or SS_METHOD_SSSP");
+    if (method != SS_METHOD_SS && method != SS_METHOD_SSSP && method != SS_METHOD_SSSP_GV)
+        return fail(SS_ERR_INVALID_ARG, "method must be SS_METHOD_SS, _SSSP or _SSSP_GV");
     if (cat->n_obj > 0 && (!logits || !best_idx || !best_period || !best_power || !obj_status))
         return fail(SS_ERR_INVALID_ARG, "null argument");
     if (cat->n_obj == 0) return SS_OK;
@@ -686,8 +701,8 @@ int ss_learned_best_period(ss_ctx *ctx, int32_t method, const ss_catalog *cat,
     if (rc != SS_OK) return rc;
     rc = check_learned(cat, top_k, margin, full_below);
     if (rc != SS_OK) return rc;
-    if (method != SS_METHOD_SS && method != SS_METHOD_SSSP)
-        return fail(SS_ERR_INVALID_ARG, "method must be SS_METHOD_SS or SS_METHOD_SSSP");
+    if (method != SS_METHOD_SS && method != SS_METHOD_SSSP && method != SS_METHOD_SSSP_GV)
+        return fail(SS_ERR_INVALID_ARG, "method must be SS_METHOD_SS, _SSSP or _SSSP_GV");
     if (!std::isfinite(gamma) || gamma < 0.0f)
         return fail(SS_ERR_INVALID_ARG, "gamma must be finite and >= 0");
     if (!enc_params && gamma == 0.0f)
@@ -752,6 +767,6 @@ int ss_enc_num_params(void) { return kEncParams; }
 
 const char *ss_last_error(void) { return g_last_error.c_str(); }
 
-int ss_version(void) { return 120; }
+int ss_version(void) { return 130; }
 
 }  // extern "C"

@@ -32,7 +32,7 @@ struct TrialLaunch {
     double span[3];
     double alpha;
     double fixed_span;
-    int32_t method;       // 0 SS, 1 SSSP
+    int32_t method;       // 0 SS, 1 SSSP (GCV per trial), 2 SSSP (GV per point)
     int32_t ext;          // periodic extension of the prefix sums (>= every b used)
     double *pgram64;      // [n_obj * n_freq] or null
     float *pgram32;       // [n_obj * n_freq] or null

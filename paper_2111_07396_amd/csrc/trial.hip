@@ -1,5 +1,6 @@
 // Fused per-trial kernel: fold -> LDS bucket sort -> Super Smoother (Listing
-// 1) or the single-pass GCV variant (Sec. 3) -> chi^2 -> P -> tile argmax.
+// 1) or the single-pass variant (Sec. 3, two readings) -> chi^2 -> P ->
+// running argmax of the work item.
 //
 // A trial group of NW wavefronts (one workgroup) owns one (object, frequency
 // tile) work item and runs its trials one after another; thread t of the
@@ -559,7 +560,13 @@ __device__ double supersmoother(const Group<P, NW, PPL> &G, const TrialLaunch &L
 }
 
 // ------------------------------------------------------------------ Sec. 3
-template <class P, int NW, int PPL>
+// One sweep over the candidate spans (smooths s_k, traces TR_k).  First
+// reading (GV = false): generalized cross-validation picks one span per
+// trial, chi^2 = RSS of that span.  Second reading (GV = true): a span per
+// point by the un-smoothed generalized-validation residual
+// |y - s_k| / (1 - TR_k/n), Listing 1's scan, bass enhancement, clip and
+// blend of the s_k, chi^2 of the blend (no residual, span or final smooth).
+template <class P, int NW, int PPL, bool GV>
 __device__ double single_pass(const Group<P, NW, PPL> &G, const TrialLaunch &L,
                               const typename P::S (&x)[PPL], const typename P::R (&w)[PPL],
                               const typename P::S (&wx)[PPL], const typename P::R (&y)[PPL]) {
@@ -601,6 +608,59 @@ __device__ double single_pass(const Group<P, NW, PPL> &G, const TrialLaunch &L,
 #pragma unroll
         for (int k = 0; k < 3; ++k)
             if (k < K) tie_average<P, NW, PPL>(G, w, s[k]);
+    }
+    if constexpr (GV) {
+        if (K == 3) {
+            double trd[3] = {P::dbl(tr[0]), P::dbl(tr[1]), P::dbl(tr[2])}, z = 0.0;
+            group_sum2<P, NW, PPL>(G, trd[0], trd[1]);
+            group_sum2<P, NW, PPL>(G, trd[2], z);
+            bool ok[3];
+            R iden[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                ok[k] = trd[k] < (double)n;
+                iden[k] = ok[k] ? (R)(1.0 / (1.0 - trd[k] / (double)n)) : R(0);
+            }
+            const R sp0 = (R)L.span[0], sp1 = (R)L.span[1], sp2 = (R)L.span[2];
+            const R spk[3] = {sp0, sp1, sp2};
+            const R ilo = R(1) / (sp0 - sp1), ihi = R(1) / (sp2 - sp1);
+            const double alpha = L.alpha;
+            const bool bass = alpha > 0.0 && alpha <= 10.0;
+            const R ex = (R)(10.0 - alpha);
+            // spans with the same half-width give the same smooth: reuse the
+            // residual so that the scan's tie rule (first span wins) sees an
+            // exact tie, as the definition does
+            const bool same01 = b[1] == b[0], same12 = b[2] == b[1];
+            R smo[PPL];
+#pragma unroll
+            for (int p = 0; p < PPL; ++p) {
+                R e[3];
+#pragma unroll
+                for (int k = 0; k < 3; ++k)
+                    e[k] = ok[k] ? P::fabs_(y[p] - s[k][p]) * iden[k] : R(__builtin_inff());
+                if (same01) e[1] = e[0];
+                if (same12) e[2] = e[1];
+                R resmin = R(1.0e20), sel = R(0);
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    const bool lt = e[k] < resmin;
+                    resmin = lt ? e[k] : resmin;
+                    sel = lt ? spk[k] : sel;
+                }
+                if (bass && resmin < e[2] && resmin > R(0)) {
+                    R tmp = resmin / e[2];
+                    if (tmp < R(1.0e-7)) tmp = R(1.0e-7);
+                    sel += (sp2 - sel) * bass_pow<P>(tmp, ex);
+                }
+                if (sel <= sp0) sel = sp0;
+                if (sel >= sp2) sel = sp2;
+                const R f = sel - sp1;
+                const bool below = f < R(0);
+                const R fr = below ? f * ilo : f * ihi;
+                smo[p] = (R(1) - fr) * s[1][p] + fr * (below ? s[0][p] : s[2][p]);
+            }
+            return chi2_of<P, NW, PPL>(G, w, y, smo);
+        }
     }
     double best = 0.0, chi2 = 0.0;
 #pragma unroll
@@ -760,7 +820,7 @@ __device__ double run_trial(Group<P, NW, PPL> &G, unsigned char *lds, const Layo
         G.vsmlsq = listing_vsmlsq(scale);
     }
     const double chi2 = (METHOD == 0) ? supersmoother<P, NW, PPL>(G, L, x, w, wx, y)
-                                      : single_pass<P, NW, PPL>(G, L, x, w, wx, y);
+                                      : single_pass<P, NW, PPL, METHOD == 2>(G, L, x, w, wx, y);
     return 1.0 - chi2 / chi0;
 }
 
@@ -876,8 +936,12 @@ hipError_t launch_one(const TrialLaunch &L, int64_t max_items, int n_cu, hipStre
 
 template <class P, int NW, int PPL>
 hipError_t launch_cls(const TrialLaunch &L, int64_t max_items, int n_cu, hipStream_t s) {
-    return L.method == 0 ? launch_one<P, NW, PPL, 0>(L, max_items, n_cu, s)
-                         : launch_one<P, NW, PPL, 1>(L, max_items, n_cu, s);
+    switch (L.method) {
+    case 0: return launch_one<P, NW, PPL, 0>(L, max_items, n_cu, s);
+    case 1: return launch_one<P, NW, PPL, 1>(L, max_items, n_cu, s);
+    case 2: return launch_one<P, NW, PPL, 2>(L, max_items, n_cu, s);
+    }
+    return hipErrorInvalidValue;
 }
 
 template <class P>
