@@ -16,19 +16,21 @@ namespace ssg {
 
 // Default trial-group shape for a light curve of n points: per method and
 // precision, the fastest shape measured on MI355X for each length range
-// (synthetic catalogs, 20,000 frequencies; single-wavefront groups win while
-// a wavefront holds the curve, SSSP prefers two wavefronts from 193 points).
+// (synthetic catalogs; each kernel with its own register budget, see
+// trial.hip): single-wavefront groups while one wavefront holds the curve at
+// up to 3 points per thread, then two wavefronts for SS and one wavefront at
+// 4 points for the single-pass methods, wider groups above.
 struct ShapeRow {
     int32_t n_max, nw, ppl;
 };
-constexpr ShapeRow kDefSS64[] = {{64, 1, 1},   {128, 1, 2},  {192, 1, 3},  {256, 1, 4},
-                                 {384, 2, 3},  {512, 4, 2},  {1024, 8, 2}, {2048, 8, 4},
-                                 {3072, 16, 3}, {4096, 16, 4}};
-constexpr ShapeRow kDefOther[] = {{64, 1, 1},   {128, 1, 2},  {192, 1, 3},  {256, 2, 2},
-                                  {384, 2, 3},  {512, 4, 2},  {1024, 8, 2}, {2048, 8, 4},
-                                  {3072, 16, 3}, {4096, 16, 4}};
-constexpr int kNumDefRows = (int)(sizeof(kDefSS64) / sizeof(kDefSS64[0]));
-static_assert(kNumDefRows == (int)(sizeof(kDefOther) / sizeof(kDefOther[0])), "tables");
+constexpr ShapeRow kDefSS[] = {{64, 1, 1},   {128, 1, 2},  {192, 1, 3},  {256, 2, 2},
+                               {384, 2, 3},  {512, 4, 2},  {1024, 8, 2}, {2048, 8, 4},
+                               {3072, 16, 3}, {4096, 16, 4}};
+constexpr ShapeRow kDefSP[] = {{64, 1, 1},   {128, 1, 2},  {192, 1, 3},  {256, 1, 4},
+                               {384, 2, 3},  {512, 4, 2},  {1024, 4, 4}, {2048, 8, 4},
+                               {3072, 16, 3}, {4096, 16, 4}};
+constexpr int kNumDefRows = (int)(sizeof(kDefSS) / sizeof(kDefSS[0]));
+static_assert(kNumDefRows == (int)(sizeof(kDefSP) / sizeof(kDefSP[0])), "tables");
 
 int shape_index(int nw, int ppl) {
     for (int s = 0; s < kNumShapes; ++s)
@@ -36,8 +38,8 @@ int shape_index(int nw, int ppl) {
     return -1;
 }
 
-const ShapeRow *default_rows(int method, int precision) {
-    return (method == 0 && precision == 0) ? kDefSS64 : kDefOther;
+const ShapeRow *default_rows(int method, int /*precision*/) {
+    return method == 0 ? kDefSS : kDefSP;
 }
 
 }  // namespace ssg

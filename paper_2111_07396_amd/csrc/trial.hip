@@ -882,11 +882,34 @@ __device__ void run_item(Group<P, NW, PPL> &G, unsigned char *lds, const Layout 
     }
 }
 
+// Minimum wavefronts per SIMD the compiler must fit each kernel into (its
+// register budget: 512 / waves registers per lane).  Measured on MI355X per
+// precision, shape and method: a budget that forces a few spills but raises
+// the resident wavefronts pays off for some kernels (up to 1.8x) and costs
+// others (the single-wavefront SS kernel at 4 points per thread loses 40 %
+// when held to two), so every kernel has its own value; 1 = no bound.
+template <bool F64, int NW, int PPL, int METHOD>
+constexpr int waves_per_simd() {
+    constexpr bool ss = METHOD == 0;
+    if (NW == 1 && PPL == 1) return (F64 && ss) ? 3 : 1;
+    if (NW == 1 && PPL == 2) return ss ? 1 : 3;
+    if (NW == 1 && PPL == 3) return (F64 && ss) ? 2 : 1;
+    if (NW == 1 && PPL == 4) return ss ? 1 : 2;
+    if (NW == 2 && PPL == 1) return ss ? 3 : 1;
+    if (NW == 2 && PPL == 2) return ss ? (F64 ? 2 : 1) : 3;
+    if (NW == 4 && PPL == 1) return ss ? 3 : 1;
+    if (NW == 2 && PPL == 3) return (F64 && ss) ? 2 : 1;
+    if (NW == 4 && PPL == 2) return ss ? (F64 ? 2 : 1) : 3;
+    if (NW == 4 && PPL == 4) return ss ? 1 : 2;
+    return 1;
+}
+
 // Persistent: every workgroup takes items from the class queue until all
 // count * n_tiles items are handed out (each workgroup exits after at most
 // one failed take).
 template <class P, int NW, int PPL, int METHOD>
-__global__ __launch_bounds__(kWave *NW) void trial_kernel(TrialLaunch L) {
+__global__ __launch_bounds__(kWave *NW, (waves_per_simd<P::kIsF64, NW, PPL, METHOD>()))
+void trial_kernel(TrialLaunch L) {
     using S = typename P::S;
     extern __shared__ __align__(16) unsigned char lds[];
     const Layout Y(NW, PPL, L.ext);
