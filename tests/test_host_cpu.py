@@ -1,0 +1,87 @@
+"""Host-side logic that needs no GPU: the library's bin table and argument
+checks, the training helpers' label binning and initialisation, the tuner's
+sub-catalog extraction, and the benchmark's one-GPU contract."""
+import ctypes
+import os
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2111_07396_amd as ssg
+from oracle import refine as ref
+from paper_2111_07396_amd import learn, synth, tune
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_labels_from_best_use_the_bin_table():
+    grid = (0.05, 20.0, 50_000)
+    tab = ref.bin_table(*grid)
+    ks = np.array([-1, 0, 1, 49_999, 12_345, int(tab[500]), int(tab[500]) - 1])
+    lab = learn.labels_from_best(ks, grid)
+    assert lab[0] == -1
+    for k, b in zip(ks[1:], lab[1:]):
+        assert tab[b] <= k < tab[b + 1]
+
+
+def test_init_params_layout():
+    p = learn.init_params(3)
+    assert p.size == ssg.ENC_PARAMS == 80 * 64 + 64 * 128 + 128 + 128 * 1024 + 1024
+    w1 = p[:80 * 64].reshape(80, 64)
+    assert np.all(w1[66:] == 0.0) and np.any(w1[:66] != 0.0)
+    b2 = p[80 * 64 + 64 * 128:80 * 64 + 64 * 128 + 128]
+    assert np.all(b2 == 0.0) and np.all(p[-1024:] == 0.0)
+
+
+def test_tuner_sub_catalog():
+    cat = synth.make_catalog(3, 7, (10, 30), 100.0, (0.5, 5.0), 0.05)
+    idx = np.array([5, 1, 3])
+    offs, t, y, e = tune._sub(cat.offsets, cat.t, cat.y, cat.e, idx)
+    assert offs[0] == 0 and len(offs) == 4
+    for j, o in enumerate(idx):
+        a, b = cat.offsets[o], cat.offsets[o + 1]
+        np.testing.assert_array_equal(t[offs[j]:offs[j + 1]], cat.t[a:b])
+        np.testing.assert_array_equal(y[offs[j]:offs[j + 1]], cat.y[a:b])
+
+
+def test_bin_table_rejects_bad_grids():
+    lib = ssg.load_library()
+    out = np.zeros(1025, dtype=np.int64)
+    for g in ((0.0, 1.0, 10), (2.0, 1.0, 10), (0.1, 1.0, 0)):
+        rc = lib.ss_bin_table(ctypes.byref(ssg._Grid(*g)), ctypes.c_void_p(out.ctypes.data))
+        assert rc == ssg.SS_ERR_INVALID_ARG
+    assert lib.ss_bin_table(None, None) == ssg.SS_ERR_INVALID_ARG
+
+
+def test_learned_calls_reject_bad_arguments_before_any_device_work():
+    lib = ssg.load_library()
+    g = ssg._Grid(0.1, 10.0, 100)
+    p = ssg._Params()
+    lib.ss_params_default(ctypes.byref(p))
+    c = ssg._Catalog(1, 10, None, None, None, None)
+    rc = lib.ss_learned_best_period(None, 0, ctypes.byref(c), ctypes.byref(g), ctypes.byref(p),
+                                    None, ctypes.c_float(1.0), 16, 0, 0, None, None, None, None,
+                                    None)
+    assert rc == ssg.SS_ERR_INVALID_ARG
+    rc = lib.ss_adam_step(None, None, None, None, 10, 1, ctypes.c_float(1e-3),
+                          ctypes.c_float(0.9), ctypes.c_float(0.999), ctypes.c_float(1e-8), None)
+    assert rc == ssg.SS_ERR_INVALID_ARG
+    rc = lib.ss_method_periodogram(None, 3, ctypes.byref(c), ctypes.byref(g), ctypes.byref(p),
+                                   None, None, None)
+    assert rc == ssg.SS_ERR_INVALID_ARG
+
+
+def test_device_catalog_requires_device_tensors():
+    cat = ssg.DeviceCatalog(torch.zeros(2, dtype=torch.int64), torch.zeros(3, dtype=torch.float64),
+                            torch.zeros(3, dtype=torch.float64), torch.zeros(3, dtype=torch.float64))
+    with pytest.raises(ValueError):
+        cat._c()
+
+
+def test_bench_refuses_more_than_one_gpu():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
