@@ -61,6 +61,9 @@ def _load():
     lib.ora_sssp.restype = ctypes.c_double
     lib.ora_sssp.argtypes = [ctypes.c_int, _dp, _dp, _dp, ctypes.c_int, _dp, ctypes.c_int,
                              ctypes.c_double, _dp, _dp, ctypes.POINTER(ctypes.c_int)]
+    lib.ora_pdm.restype = ctypes.c_double
+    lib.ora_pdm.argtypes = [ctypes.c_int, _dp, _dp, _dp, ctypes.c_double, ctypes.c_double,
+                            ctypes.c_double, ctypes.c_int]
     lib.ora_sssp2.restype = ctypes.c_double
     lib.ora_sssp2.argtypes = [ctypes.c_int, _dp, _dp, _dp, ctypes.c_int, _dp, ctypes.c_double,
                               ctypes.c_double]
@@ -171,6 +174,35 @@ def sssp(x, y, w, spans=DEFAULT_SPANS, fixed_span=0.0, periodic=True):
     chi2 = _load().ora_sssp(x.size, xp, yp, wp, 2 if periodic else 1, spp, K, fixed_span, rp, tp,
                             ctypes.byref(kb))
     return float(chi2), rss, tr, kb.value
+
+
+def pdm_bins(n, n_bins=0):
+    """Phase bins of the dispersion score: n_bins, or clamp(n // 5, 4, 32) when 0."""
+    return int(n_bins) if n_bins > 0 else min(32, max(4, n // 5))
+
+
+def pdm_periodogram(offsets, t, y, e, fmin, fmax, n_freq, n_bins=0, ks=None):
+    """Phase-dispersion score of every object at every (selected) grid
+    frequency; NaN rows for objects with a bad status."""
+    lib = _load()
+    offsets = np.asarray(offsets, dtype=np.int64)
+    n_obj = offsets.size - 1
+    kk = np.arange(n_freq) if ks is None else np.asarray(ks, dtype=np.int64)
+    out = np.full((n_obj, kk.size), np.nan)
+    for o in range(n_obj):
+        a, b = offsets[o], offsets[o + 1]
+        st, tt, w, ybar, chi0 = prep(t[a:b], y[a:b], e[a:b])
+        if st != 0:
+            continue
+        ttp = tt.ctypes.data_as(_dp)
+        yy = np.ascontiguousarray(y[a:b], dtype=np.float64)
+        yp = yy.ctypes.data_as(_dp)
+        wp = w.ctypes.data_as(_dp)
+        B = pdm_bins(b - a, n_bins)
+        for i, k in enumerate(kk):
+            out[o, i] = lib.ora_pdm(int(b - a), ttp, yp, wp, ybar, chi0,
+                                    freq(fmin, fmax, n_freq, int(k)), B)
+    return out
 
 
 def sssp2(x, y, w, spans=DEFAULT_SPANS, alpha=9.0, fixed_span=0.0, periodic=True):

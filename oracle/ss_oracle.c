@@ -39,6 +39,10 @@
  *                   generalized-validation residual |y - s_k| / (1 - TR_k/n)
  *                   with Listing 1's scan, bass enhancement, clip and blend
  *                   (its residual, span and final smooths left out).
+ *   ora_pdm         Phase dispersion of one trial (a second period finder on the
+ *                   same fold; Sec. 6 names reusing the fold and sort for other
+ *                   finders): the points' phases in B equal bins, the fraction
+ *                   of chi0 explained by the bins' weighted means.
  *   ora_trial       fold -> sort -> smoother -> chi^2 -> P = 1 - chi^2/chi0
  *                   (Alg. 1 computePgram; formula read as stated).
  *   ora_periodogram Alg. 1 over a catalog of objects (Sec. 4.3 batch mode).
@@ -480,6 +484,31 @@ double ora_sssp2(int n, const double *x, const double *y, const double *w, int i
     }
     free(buf);
     return chi2;
+}
+
+/* Phase dispersion score of one trial: phase = (tt mod p)/p, bin =
+ * floor(phase B) (clamped to B - 1), score = sum_b (sum w (y - ybar))^2 /
+ * (sum w) over the non-empty bins, divided by chi0; ybar is the weighted
+ * mean.  The bins need no sort. */
+double ora_pdm(int n, const double *tt, const double *y, const double *w, double ybar,
+               double chi0, double f, int B)
+{
+    double *ph = (double *)malloc((size_t)n * sizeof(double));
+    double *acc = (double *)calloc((size_t)(2 * B), sizeof(double));
+    ora_fold(n, tt, f, ph);
+    for (int i = 0; i < n; ++i) {
+        int b = (int)floor(ph[i] * (double)B);
+        if (b > B - 1) b = B - 1;
+        if (b < 0) b = 0;
+        acc[b] += w[i];
+        acc[B + b] += w[i] * (y[i] - ybar);
+    }
+    double e = 0.0;
+    for (int b = 0; b < B; ++b)
+        if (acc[b] > 0.0) e += acc[B + b] * acc[B + b] / acc[b];
+    free(acc);
+    free(ph);
+    return e / chi0;
 }
 
 /* ------------------------------------------------------------------ one trial */

@@ -367,3 +367,45 @@ def test_argsort_is_stable():
 def test_best_lowest_index_and_nan():
     assert oracle.best(np.array([0.1, 0.5, np.nan, 0.5, 0.2])) == 1
     assert oracle.best(np.array([np.nan, np.nan])) == -1
+
+
+# ----------------------------------------------------------------- phase dispersion
+
+def test_pdm_equals_anova_between_groups():
+    # equal weights: the score is the between-group sum of squares over the
+    # total, which follows from scipy's one-way ANOVA F statistic
+    from scipy.stats import f_oneway
+    rng = np.random.default_rng(8)
+    n, B = 97, 7
+    t = np.sort(rng.uniform(0, 80, n))
+    y = rng.normal(size=n)
+    e = np.full(n, 0.3)
+    f = 0.731
+    st, tt, w, ybar, chi0 = oracle.prep(t, y, e)
+    p = oracle.pdm_periodogram(np.array([0, n]), t, y, e, f, 2 * f, 1, n_bins=B)[0, 0]
+    ph = oracle.fold(tt, f)
+    g = np.minimum(B - 1, np.floor(ph * B).astype(int))
+    groups = [y[g == b] for b in range(B) if np.any(g == b)]
+    F = f_oneway(*groups).statistic
+    k = len(groups)
+    sst = np.sum((y - y.mean()) ** 2)
+    ssb = sst * F * (k - 1) / (F * (k - 1) + (n - k))
+    assert p == pytest.approx(ssb / sst, rel=1e-10)
+
+
+def test_pdm_step_curve_scores_one_and_constant_zero():
+    n, B = 40, 8
+    t = np.arange(n) * 2.0 ** -5          # exact phases j/40 at f = 0.8
+    y = np.where(np.arange(n) < 5, 1.0, 0.0) + 3.0
+    e = np.ones(n)
+    f0 = 1.0 / (n * 2.0 ** -5)
+    p = oracle.pdm_periodogram(np.array([0, n]), t, y, e, f0, 2 * f0, 1, n_bins=B)[0, 0]
+    assert p == pytest.approx(1.0, abs=1e-12)
+    e2 = oracle.pdm_periodogram(np.array([0, n]), t, np.full(n, 2.0), e, f0, 2 * f0, 1)
+    assert np.isnan(e2).all()  # constant magnitudes: bad status, NaN row
+
+
+def test_pdm_bins_rule():
+    assert [oracle.pdm_bins(n) for n in (5, 20, 21, 100, 160, 161, 5000)] == \
+        [4, 4, 4, 20, 32, 32, 32]
+    assert oracle.pdm_bins(100, 9) == 9
