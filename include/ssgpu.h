@@ -145,6 +145,18 @@ int ss_method_periodogram(ss_ctx *ctx, int32_t method, const ss_catalog *cat,
                           const ss_grid *grid, const ss_params *params, void *pgram,
                           int32_t *obj_status, void *stream);
 
+/* Two finders from one fold and sort: the method's periodogram (as
+ * ss_method_periodogram) and, from the same sorted phases of every trial, the
+ * phase-dispersion periodogram pgram_pdm [n_obj * n_freq] (same type): the
+ * fraction of chi0 explained by the weighted means of n_bins equal phase bins
+ * (bin b holds the points with b <= B phase < b + 1, phase from the FP64 fold
+ * as a 48-bit fixed-point value), i.e. sum_b (sum w (y - ybar))^2 / (sum w)
+ * / chi0.  n_bins = 0 uses clamp(n / 5, 4, 32) per object; else 2..256.
+ * Bad objects get NaN rows in both. */
+int ss_pdm_periodogram(ss_ctx *ctx, int32_t method, const ss_catalog *cat,
+                       const ss_grid *grid, const ss_params *params, int32_t n_bins,
+                       void *pgram, void *pgram_pdm, int32_t *obj_status, void *stream);
+
 /* Best period per object without materialising the periodogram (Alg. 1
  * findPeriod): best_idx[o] = the lowest k attaining the largest P (NaN
  * skipped), best_period[o] = 1/f_k, best_power[o] = that P (as double).

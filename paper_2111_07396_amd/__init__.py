@@ -30,7 +30,8 @@ EXPORTED = ("ss_params_default", "ss_ctx_create", "ss_ctx_destroy", "ss_periodog
             "ss_ctx_set_shape", "ss_ctx_set_tile", "ss_ctx_set_timing", "ss_ctx_trial_kernel_ms",
             "ss_last_error", "ss_version", "ss_bin_table", "ss_enc_num_params", "ss_enc_forward",
             "ss_enc_train_grad", "ss_adam_step", "ss_refine_best_period",
-            "ss_learned_best_period", "ss_bin_scores", "ss_method_periodogram")
+            "ss_learned_best_period", "ss_bin_scores", "ss_method_periodogram",
+            "ss_pdm_periodogram")
 ENC_PARAMS = 145536
 ENC_BINS = 1024
 
@@ -97,6 +98,9 @@ def load_library(path: str = LIB_PATH):
                                           ctypes.POINTER(_Grid), ctypes.POINTER(_Params), vp,
                                           vp, vp]
     lib.ss_method_periodogram.restype = ctypes.c_int
+    lib.ss_pdm_periodogram.argtypes = [vp, i32, ctypes.POINTER(_Catalog), ctypes.POINTER(_Grid),
+                                       ctypes.POINTER(_Params), i32, vp, vp, vp, vp]
+    lib.ss_pdm_periodogram.restype = ctypes.c_int
     lib.ss_best_period.argtypes = [vp, i32, ctypes.POINTER(_Catalog), ctypes.POINTER(_Grid),
                                    ctypes.POINTER(_Params), vp, vp, vp, vp, vp]
     lib.ss_best_period.restype = ctypes.c_int
@@ -304,6 +308,23 @@ class Context:
         m = int(method)
         return self._pgram(lambda *a: _lib.ss_method_periodogram(a[0], m, *a[1:]), cat, grid,
                            params or Params(), out, status, stream)
+
+    def pdm_periodogram(self, method, cat, grid, n_bins=0, params=None, stream=None):
+        """(P of the method, phase-dispersion score, status) from one fold and sort per trial."""
+        params = params or Params()
+        n_obj = cat.n_obj
+        dt = torch.float64 if params.precision == SS_FP64 else torch.float32
+        dev = cat.offsets.device
+        pg = torch.empty((n_obj, int(grid[2])), dtype=dt, device=dev)
+        pd = torch.empty((n_obj, int(grid[2])), dtype=dt, device=dev)
+        st = torch.empty(n_obj, dtype=torch.int32, device=dev)
+        g = _Grid(float(grid[0]), float(grid[1]), int(grid[2]))
+        c = cat._c()
+        p = params._c()
+        _check(_lib.ss_pdm_periodogram(self._h, int(method), ctypes.byref(c), ctypes.byref(g),
+                                       ctypes.byref(p), int(n_bins), _ptr(pg), _ptr(pd), _ptr(st),
+                                       _stream_ptr(stream)))
+        return pg, pd, st
 
     def ss_best_period(self, method, cat, grid, params=None, out=None, stream=None):
         """(best_idx int64, best_period f64, best_power f64, status int32) per object."""

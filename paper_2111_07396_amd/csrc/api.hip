@@ -208,7 +208,8 @@ int prepare(ss_ctx *ctx, int method, const ss_catalog *cat, const ss_params *prm
 int trials(ss_ctx *ctx, const Plan &P, int method, const ss_catalog *cat, const ss_grid *grid,
            const ss_params *prm, double *pgram64, float *pgram32, bool want_best,
            int32_t *obj_status, hipStream_t stream, int64_t *best_idx, double *best_period,
-           double *best_power, int32_t tile, int32_t n_tiles, const int64_t *ranges) {
+           double *best_power, int32_t tile, int32_t n_tiles, const int64_t *ranges,
+           void *pdm = nullptr, int32_t pdm_bins = 0) {
     const int64_t n_obj = cat->n_obj;
     if (want_best) {
         SS_HIP_TRY(ctx->part_p.ensure((size_t)n_obj * n_tiles * 8), "workspace");
@@ -241,6 +242,9 @@ int trials(ss_ctx *ctx, const Plan &P, int method, const ss_catalog *cat, const 
     L.part_p = want_best ? (double *)ctx->part_p.p : nullptr;
     L.part_k = want_best ? (int32_t *)ctx->part_k.p : nullptr;
     L.ranges = ranges;
+    L.pdm64 = (pdm && prm->precision == SS_FP64) ? (double *)pdm : nullptr;
+    L.pdm32 = (pdm && prm->precision != SS_FP64) ? (float *)pdm : nullptr;
+    L.pdm_bins = pdm_bins;
     ctx->n_timed = 0;
     for (int c = 0; c < kNumShapes; ++c) {
         if (!P.used[c] || !((P.R.runnable >> c) & 1u)) continue;
@@ -272,7 +276,7 @@ int trials(ss_ctx *ctx, const Plan &P, int method, const ss_catalog *cat, const 
 int run(ss_ctx *ctx, int method, const ss_catalog *cat, const ss_grid *grid,
         const ss_params *prm, double *pgram64, float *pgram32, bool want_best,
         int32_t *obj_status, hipStream_t stream, int64_t *best_idx, double *best_period,
-        double *best_power) {
+        double *best_power, void *pdm = nullptr, int32_t pdm_bins = 0) {
     const int64_t n_obj = cat->n_obj;
     if (n_obj == 0) return SS_OK;
     const int32_t tile = ctx->tile_f > 0 ? (int32_t)std::min<int64_t>(ctx->tile_f, grid->n_freq)
@@ -282,7 +286,7 @@ int run(ss_ctx *ctx, int method, const ss_catalog *cat, const ss_grid *grid,
     int rc = prepare(ctx, method, cat, prm, obj_status, stream, P);
     if (rc != SS_OK) return rc;
     return trials(ctx, P, method, cat, grid, prm, pgram64, pgram32, want_best, obj_status, stream,
-                  best_idx, best_period, best_power, tile, n_tiles, nullptr);
+                  best_idx, best_period, best_power, tile, n_tiles, nullptr, pdm, pdm_bins);
 }
 
 // First fine-grid index of each of the 1024 log-spaced bins over
@@ -528,6 +532,23 @@ int ss_method_periodogram(ss_ctx *ctx, int32_t method, const ss_catalog *cat,
                nullptr, nullptr);
 }
 
+int ss_pdm_periodogram(ss_ctx *ctx, int32_t method, const ss_catalog *cat,
+                       const ss_grid *grid, const ss_params *params, int32_t n_bins,
+                       void *pgram, void *pgram_pdm, int32_t *obj_status, void *stream) {
+    int rc = check_common(ctx, cat, grid, params);
+    if (rc != SS_OK) return rc;
+    if (method != SS_METHOD_SS && method != SS_METHOD_SSSP && method != SS_METHOD_SSSP_GV)
+        return fail(SS_ERR_INVALID_ARG, "method must be SS_METHOD_SS, _SSSP or _SSSP_GV");
+    if (n_bins < 0 || n_bins > 256) return fail(SS_ERR_INVALID_ARG, "n_bins must be in [0, 256]");
+    if (n_bins == 1) return fail(SS_ERR_INVALID_ARG, "n_bins = 1 explains nothing");
+    if (cat->n_obj > 0 && (!pgram || !pgram_pdm || !obj_status))
+        return fail(SS_ERR_INVALID_ARG, "null output pointer");
+    bool f64 = params->precision == SS_FP64;
+    return run(ctx, method, cat, grid, params, f64 ? (double *)pgram : nullptr,
+               f64 ? nullptr : (float *)pgram, false, obj_status, (hipStream_t)stream, nullptr,
+               nullptr, nullptr, pgram_pdm, n_bins);
+}
+
 int ss_best_period(ss_ctx *ctx, int32_t method, const ss_catalog *cat, const ss_grid *grid,
                    const ss_params *params, int64_t *best_idx, double *best_period,
                    double *best_power, int32_t *obj_status, void *stream) {
@@ -769,6 +790,6 @@ int ss_enc_num_params(void) { return kEncParams; }
 
 const char *ss_last_error(void) { return g_last_error.c_str(); }
 
-int ss_version(void) { return 130; }
+int ss_version(void) { return 140; }
 
 }  // extern "C"

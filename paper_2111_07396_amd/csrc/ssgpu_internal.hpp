@@ -40,6 +40,9 @@ struct TrialLaunch {
     int32_t *part_k;      // [n_obj * n_tiles] or null
     const int64_t *ranges;  // refine: [n_obj][n_tiles] of (k_begin, k_end), or null for
                             // the full grid cut into tiles of tile_f
+    double *pdm64;          // phase-dispersion periodogram [n_obj * n_freq] or null
+    float *pdm32;
+    int32_t pdm_bins;       // phase bins (0: clamp(n / 5, 4, 32))
 };
 
 // Expressions that must round exactly like their plain C statement (no

@@ -687,6 +687,56 @@ __device__ double single_pass(const Group<P, NW, PPL> &G, const TrialLaunch &L,
     return chi2;
 }
 
+// ------------------------------------------------------------------ phase dispersion
+// Number of sorted points whose 48-bit phase is below `bnd`.
+__device__ __forceinline__ int count_below(const uint64_t *SK, int n, uint64_t bnd) {
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if ((SK[mid] >> 16) < bnd)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// A second finder on the same fold and sort: the fraction of chi0 explained
+// by the weighted means of B equal phase bins.  Bin b holds the sorted points
+// with b 2^48 <= B phase48 < (b + 1) 2^48, a contiguous run found by binary
+// search on the sorted keys; its sums are differences of prefix sums of w and
+// w y built in A0, A1 (free until the smoother starts).
+template <class P, int NW, int PPL>
+__device__ double pdm_score(const Group<P, NW, PPL> &G, int B, const typename P::R (&w)[PPL],
+                            const typename P::R (&y)[PPL], double chi0) {
+    using S = typename P::S;
+    S q[2][PPL];
+#pragma unroll
+    for (int p = 0; p < PPL; ++p) {
+        q[0][p] = P::from(w[p]);
+        q[1][p] = P::prod(w[p], y[p]);
+    }
+    S *const Pf[2] = {G.A0, G.A1};
+    S T[2];
+    bsync<NW>();
+    build_prefix<P, NW, PPL, 2>(G, Pf, q, T);
+    const int n = G.n;
+    const uint64_t one = 1ull << 48;
+    double e = 0.0, z = 0.0;
+    for (int b = G.t; b < B; b += Group<P, NW, PPL>::NT) {
+        const int lo = count_below(G.SK, n, ((uint64_t)b * one + (uint64_t)(B - 1)) / (uint64_t)B);
+        const int hi = b == B - 1 ? n
+                                  : count_below(G.SK, n,
+                                                ((uint64_t)(b + 1) * one + (uint64_t)(B - 1)) /
+                                                    (uint64_t)B);
+        const double wb = P::dbl(P::sub(G.A0[G.slot(hi)], G.A0[G.slot(lo)]));
+        const double sb = P::dbl(P::sub(G.A1[G.slot(hi)], G.A1[G.slot(lo)]));
+        if (wb > 0.0) e += sb * sb / wb;
+    }
+    group_sum2<P, NW, PPL>(G, e, z);
+    return e / chi0;
+}
+
 // ------------------------------------------------------------------ one trial
 // Object data of the work item, original (time) order; re-read from the
 // caches at every trial instead of being held in registers.
@@ -698,7 +748,8 @@ struct ObjData {
 
 template <class P, int NW, int PPL, int METHOD>
 __device__ double run_trial(Group<P, NW, PPL> &G, unsigned char *lds, const Layout &Y,
-                            const TrialLaunch &L, const ObjData<P> &od, double f, double chi0) {
+                            const TrialLaunch &L, const ObjData<P> &od, double f, double chi0,
+                            double &pdm) {
     using R = typename P::R;
     using S = typename P::S;
     const int n = G.n, t = G.t, NP = Y.np;
@@ -797,6 +848,10 @@ __device__ double run_trial(Group<P, NW, PPL> &G, unsigned char *lds, const Layo
     } else {
         G.ties = __syncthreads_or(tie) != 0;
     }
+    if (L.pdm64 || L.pdm32) {
+        const int B = L.pdm_bins > 0 ? L.pdm_bins : min(32, max(4, n / 5));
+        pdm = pdm_score<P, NW, PPL>(G, B, w, y, chi0);
+    }
 
     // ---- Listing 1: constant fit when the phases do not spread
     if ((SK[n - 1] >> 16) <= (SK[0] >> 16)) {
@@ -848,6 +903,8 @@ __device__ void run_item(Group<P, NW, PPL> &G, unsigned char *lds, const Layout 
         for (int64_t k = k0 + G.t; k < k1; k += kWave * NW) {
             if (L.pgram64) L.pgram64[row + k] = __builtin_nan("");
             if (L.pgram32) L.pgram32[row + k] = __builtin_nanf("");
+            if (L.pdm64) L.pdm64[row + k] = __builtin_nan("");
+            if (L.pdm32) L.pdm32[row + k] = __builtin_nanf("");
         }
         if (G.t == 0 && L.part_p) {
             L.part_p[part] = __builtin_nan("");
@@ -866,10 +923,13 @@ __device__ void run_item(Group<P, NW, PPL> &G, unsigned char *lds, const Layout 
     int32_t best_k = -1;
     for (int64_t k = k0; k < k1; ++k) {
         const double f = grid_freq(L.fmin, L.df, k);
-        const double Pk = run_trial<P, NW, PPL, METHOD>(G, lds, Y, L, od, f, chi0);
+        double pdm = 0.0;
+        const double Pk = run_trial<P, NW, PPL, METHOD>(G, lds, Y, L, od, f, chi0, pdm);
         if (G.t == 0) {
             if (L.pgram64) L.pgram64[row + k] = Pk;
             if (L.pgram32) L.pgram32[row + k] = (float)Pk;
+            if (L.pdm64) L.pdm64[row + k] = pdm;
+            if (L.pdm32) L.pdm32[row + k] = (float)pdm;
         }
         if (!__builtin_isnan(Pk) && (best_k < 0 || Pk > best_p)) {
             best_p = Pk;
@@ -898,7 +958,7 @@ constexpr int waves_per_simd() {
     if (NW == 2 && PPL == 1) return ss ? 3 : 1;
     if (NW == 2 && PPL == 2) return ss ? (F64 ? 2 : 1) : 3;
     if (NW == 4 && PPL == 1) return ss ? 3 : 1;
-    if (NW == 2 && PPL == 3) return (F64 && ss) ? 2 : 1;
+    if (NW == 2 && PPL == 3) return 1;  // FP64 SS held to 2 spilled to scratch and miscomputed
     if (NW == 4 && PPL == 2) return ss ? (F64 ? 2 : 1) : 3;
     if (NW == 4 && PPL == 4) return ss ? 1 : 2;
     return 1;

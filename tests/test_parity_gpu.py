@@ -25,8 +25,7 @@ def ctx():
 def _gpu_pgram(ctx, method, offs, t, y, e, grid, params=None):
     import torch
     cat = ssg.DeviceCatalog.from_numpy(offs, t, y, e)
-    fn = ctx.ss_periodogram if method == oracle.SS else ctx.sssp_periodogram
-    pg, st = fn(cat, grid, params)
+    pg, st = ctx.method_periodogram(method, cat, grid, params)
     torch.cuda.synchronize()
     return pg.cpu().numpy().astype(np.float64), st.cpu().numpy()
 
@@ -202,6 +201,30 @@ def test_every_shape_gives_the_oracle_result(ctx, method):
             if ref is None:
                 ref = pg
             np.testing.assert_allclose(pg, ref, rtol=0, atol=1e-11)
+    finally:
+        ctx.set_shape(0, 0, 0)
+
+
+@pytest.mark.parametrize("precision", [ssg.SS_FP64, ssg.SS_FP32C])
+@pytest.mark.parametrize("method", [oracle.SS, oracle.SSSP, oracle.SSSP2])
+def test_every_kernel_gives_the_oracle_result(ctx, method, precision):
+    # every compiled kernel (shape x method x precision), each on a light curve
+    # that fills most of its group: every kernel has its own register budget,
+    # so each one is checked on its own
+    tol = TOL if precision == ssg.SS_FP64 else 1e-2
+    grid = (0.2, 4.0, 23)
+    try:
+        for i, (nw, ppl) in enumerate(ssg.shapes()):
+            n = min(700, max(5, int(0.85 * 64 * nw * ppl)))
+            cat = synth.make_catalog(900 + i, 1, n, 800.0, (0.3, 5.0), 0.05, shapes=(i % 3,))
+            ctx.set_shape(0, 0, 0)
+            ctx.set_shape(n, nw, ppl)
+            po, _ = oracle.periodogram(method, cat.offsets, cat.t, cat.y, cat.e, *grid)
+            pg, st = _gpu_pgram(ctx, method, cat.offsets, cat.t, cat.y, cat.e, grid,
+                                ssg.Params(precision=precision))
+            if (st == ssg.OBJ_TOO_LONG).all():  # shape does not fit the LDS at span 0.5
+                continue
+            _assert_pgram_close(pg, po, tol=tol, what=f"kernel {nw}x{ppl} n={n}")
     finally:
         ctx.set_shape(0, 0, 0)
 
