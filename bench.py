@@ -47,7 +47,7 @@ def _src_hash() -> str:
     the learned-proposal declarations in the internal header)."""
     csrc = os.path.join(ROOT, "paper_2111_07396_amd", "csrc")
     h = hashlib.sha256()
-    for name in ("trial.hip", "numeric.hpp", "wave.hpp"):
+    for name in ("trial_impl.hpp", "trial_f64.hip", "trial_f32c.hip", "numeric.hpp", "wave.hpp"):
         with open(os.path.join(csrc, name), "rb") as f:
             h.update(f.read())
     with open(os.path.join(csrc, "ssgpu_internal.hpp"), "rb") as f:

@@ -17,7 +17,7 @@ namespace ssg {
 // Default trial-group shape for a light curve of n points: per method and
 // precision, the fastest shape measured on MI355X for each length range
 // (synthetic catalogs; each kernel with its own register budget, see
-// trial.hip): single-wavefront groups while one wavefront holds the curve at
+// trial_impl.hpp): single-wavefront groups while one wavefront holds the curve at
 // up to 3 points per thread, then two wavefronts for SS and one wavefront at
 // 4 points for the single-pass methods, wider groups above.
 struct ShapeRow {

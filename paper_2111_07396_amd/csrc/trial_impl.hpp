@@ -1,4 +1,5 @@
-// Fused per-trial kernel: fold -> LDS bucket sort -> Super Smoother (Listing
+// Fused per-trial kernel (templates; instantiated per precision policy in
+// trial_f64.hip and trial_f32c.hip): fold -> LDS bucket sort -> Super Smoother (Listing
 // 1) or the single-pass variant (Sec. 3, two readings) -> chi^2 -> P ->
 // running argmax of the work item.
 //
@@ -20,6 +21,7 @@
 // Only three prefix arrays are live at any time.  With PPL even, the arrays
 // get one pad slot per PPL slots so that the threads' reads at a common
 // offset fall in distinct LDS banks.
+#pragma once
 #include "numeric.hpp"
 #include "ssgpu_internal.hpp"
 #include "wave.hpp"
@@ -746,7 +748,7 @@ struct ObjData {
     const typename P::R *y, *w;
 };
 
-template <class P, int NW, int PPL, int METHOD>
+template <class P, int NW, int PPL, int METHOD, bool PDM>
 __device__ double run_trial(Group<P, NW, PPL> &G, unsigned char *lds, const Layout &Y,
                             const TrialLaunch &L, const ObjData<P> &od, double f, double chi0,
                             double &pdm) {
@@ -848,7 +850,7 @@ __device__ double run_trial(Group<P, NW, PPL> &G, unsigned char *lds, const Layo
     } else {
         G.ties = __syncthreads_or(tie) != 0;
     }
-    if (L.pdm64 || L.pdm32) {
+    if constexpr (PDM) {
         const int B = L.pdm_bins > 0 ? L.pdm_bins : min(32, max(4, n / 5));
         pdm = pdm_score<P, NW, PPL>(G, B, w, y, chi0);
     }
@@ -881,7 +883,7 @@ __device__ double run_trial(Group<P, NW, PPL> &G, unsigned char *lds, const Layo
 
 // One work item: an object and a run of consecutive trial frequencies (a tile
 // of the full grid, or one refine range).
-template <class P, int NW, int PPL, int METHOD>
+template <class P, int NW, int PPL, int METHOD, bool PDM>
 __device__ void run_item(Group<P, NW, PPL> &G, unsigned char *lds, const Layout &Y,
                          const TrialLaunch &L, int64_t item) {
     using R = typename P::R;
@@ -924,7 +926,7 @@ __device__ void run_item(Group<P, NW, PPL> &G, unsigned char *lds, const Layout 
     for (int64_t k = k0; k < k1; ++k) {
         const double f = grid_freq(L.fmin, L.df, k);
         double pdm = 0.0;
-        const double Pk = run_trial<P, NW, PPL, METHOD>(G, lds, Y, L, od, f, chi0, pdm);
+        const double Pk = run_trial<P, NW, PPL, METHOD, PDM>(G, lds, Y, L, od, f, chi0, pdm);
         if (G.t == 0) {
             if (L.pgram64) L.pgram64[row + k] = Pk;
             if (L.pgram32) L.pgram32[row + k] = (float)Pk;
@@ -967,8 +969,9 @@ constexpr int waves_per_simd() {
 // Persistent: every workgroup takes items from the class queue until all
 // count * n_tiles items are handed out (each workgroup exits after at most
 // one failed take).
-template <class P, int NW, int PPL, int METHOD>
-__global__ __launch_bounds__(kWave *NW, (waves_per_simd<P::kIsF64, NW, PPL, METHOD>()))
+template <class P, int NW, int PPL, int METHOD, bool PDM>
+__global__ __launch_bounds__(kWave *NW,
+                             (PDM ? 1 : waves_per_simd<P::kIsF64, NW, PPL, METHOD>()))
 void trial_kernel(TrialLaunch L) {
     using S = typename P::S;
     extern __shared__ __align__(16) unsigned char lds[];
@@ -995,14 +998,14 @@ void trial_kernel(TrialLaunch L) {
         bsync<NW>();
         const unsigned long long item = *take;
         if (item >= total) break;
-        run_item<P, NW, PPL, METHOD>(G, lds, Y, L, (int64_t)item);
+        run_item<P, NW, PPL, METHOD, PDM>(G, lds, Y, L, (int64_t)item);
     }
 }
 
-template <class P, int NW, int PPL, int METHOD>
-hipError_t launch_one(const TrialLaunch &L, int64_t max_items, int n_cu, hipStream_t s) {
+template <class P, int NW, int PPL, int METHOD, bool PDM>
+hipError_t launch_variant(const TrialLaunch &L, int64_t max_items, int n_cu, hipStream_t s) {
     const Layout Y(NW, PPL, L.ext);
-    const void *fn = (const void *)trial_kernel<P, NW, PPL, METHOD>;
+    const void *fn = (const void *)trial_kernel<P, NW, PPL, METHOD, PDM>;
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, Y.bytes);
     if (e != hipSuccess) return e;
     int per_cu = 0;
@@ -1012,9 +1015,17 @@ hipError_t launch_one(const TrialLaunch &L, int64_t max_items, int n_cu, hipStre
     int64_t grid = (int64_t)per_cu * n_cu;
     if (grid > max_items) grid = max_items;
     if (grid < 1) grid = 1;
-    hipLaunchKernelGGL((trial_kernel<P, NW, PPL, METHOD>), dim3((unsigned)grid), dim3(kWave * NW),
-                       (size_t)Y.bytes, s, L);
+    hipLaunchKernelGGL((trial_kernel<P, NW, PPL, METHOD, PDM>), dim3((unsigned)grid),
+                       dim3(kWave * NW), (size_t)Y.bytes, s, L);
     return hipGetLastError();
+}
+
+// The phase-dispersion finder is its own kernel variant, so that the plain
+// kernels keep their register allocation.
+template <class P, int NW, int PPL, int METHOD>
+hipError_t launch_one(const TrialLaunch &L, int64_t max_items, int n_cu, hipStream_t s) {
+    return (L.pdm64 || L.pdm32) ? launch_variant<P, NW, PPL, METHOD, true>(L, max_items, n_cu, s)
+                                : launch_variant<P, NW, PPL, METHOD, false>(L, max_items, n_cu, s);
 }
 
 template <class P, int NW, int PPL>
@@ -1040,15 +1051,4 @@ hipError_t launch_policy(int shape, const TrialLaunch &L, int64_t max_items, int
 }
 
 }  // namespace
-
-int trial_lds_bytes(int nw, int ppl, int ext) { return Layout(nw, ppl, ext).bytes; }
-
-int trial_halfwidth(int n, double span) { return halfwidth(n, span); }
-
-hipError_t launch_trials(int shape, int precision, const TrialLaunch &L, int64_t max_items,
-                         int n_cu, hipStream_t s) {
-    return precision == 0 ? launch_policy<F64>(shape, L, max_items, n_cu, s)
-                          : launch_policy<F32C>(shape, L, max_items, n_cu, s);
-}
-
 }  // namespace ssg
