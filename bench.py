@@ -226,17 +226,24 @@ def _proposal(ctx, ssg, synth, args):
     cat5, grid5 = synth.catalog_mixed(n_obj=args.learned_objects)
     dc5 = ssg.DeviceCatalog.from_numpy(cat5.offsets, cat5.t, cat5.y, cat5.e)
     full5 = ctx.ss_best_period(ssg.SS_METHOD_SS, dc5, grid5)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    full5 = ctx.ss_best_period(ssg.SS_METHOD_SS, dc5, grid5, out=full5)
+    torch.cuda.synchronize()
+    t_full = time.perf_counter() - t0
     pol = dict(learn.POLICY)
     rl = {"sample": f"{cat5.n_obj} objects of the mixed-stream generator (N log-uniform "
                     f"[20, 1000]), {grid5[2]} frequencies on [{grid5[0]}, {grid5[1]}), SS FP64",
           "policy": pol}
-    rl["bin_scores_then_refine"] = learn.compare(ctx, dc5, grid5, None, full=full5, **pol)
+    rl["bin_scores_then_refine"] = learn.compare(ctx, dc5, grid5, None, full=full5,
+                                                 t_full=t_full, **pol)
     if os.path.exists(ENCODER_WEIGHTS):
         w = torch.tensor(np.load(ENCODER_WEIGHTS), dtype=torch.float32, device="cuda")
         rl["encoder_plus_100x_bin_scores"] = learn.compare(
-            ctx, dc5, grid5, w, 100.0, pol["top_k"], pol["margin"], pol["full_below"], full=full5)
+            ctx, dc5, grid5, w, 100.0, pol["top_k"], pol["margin"], pol["full_below"], full=full5,
+            t_full=t_full)
         rl["encoder_only"] = learn.compare(ctx, dc5, grid5, w, 0.0, pol["top_k"], pol["margin"],
-                                           pol["full_below"], full=full5)
+                                           pol["full_below"], full=full5, t_full=t_full)
     ex["proposal_vs_full"] = rl
     ex["proposal_kernels"] = _proposal_kernels(ctx, ssg, dc5, grid5, cat5)
     return ex

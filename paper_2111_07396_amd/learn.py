@@ -112,9 +112,11 @@ def topk_recall(ctx, dc: DeviceCatalog, grid, params, labels: np.ndarray, top_k:
 
 
 def compare(ctx, dc: DeviceCatalog, grid, params, gamma=0.0, top_k=16, margin=1, full_below=0,
-            method=SS_METHOD_SS, precision=SS_FP64, repeats: int = 2, full=None):
+            method=SS_METHOD_SS, precision=SS_FP64, repeats: int = 2, full=None,
+            t_full=None):
     """Agreement and wall times of proposal+refine against the full grid
-    (params = encoder weights or None; gamma = weight of the bin scores).
+    (params = encoder weights or None; gamma = weight of the bin scores;
+    full / t_full: a full-grid result and its wall time, to reuse).
     Agreement: the refined best index is the full-grid one, or its power is
     within 1e-4 (1 - P) of the full-grid best power (equal maxima)."""
     prm = Params(precision=precision)
@@ -135,7 +137,8 @@ def compare(ctx, dc: DeviceCatalog, grid, params, gamma=0.0, top_k=16, margin=1,
             best = dt if best is None else min(best, dt)
         return best
 
-    t_full = timed(lambda: ctx.ss_best_period(method, dc, grid, prm, out=full))
+    if t_full is None:
+        t_full = timed(lambda: ctx.ss_best_period(method, dc, grid, prm, out=full))
     t_lrn = timed(lambda: ctx.learned_best_period(method, dc, grid, params, gamma, top_k, margin,
                                                   full_below, prm, out=lrn))
     fi, li = full[0].cpu().numpy(), lrn[0].cpu().numpy()
