@@ -156,9 +156,11 @@ __device__ __forceinline__ bool obj_setup(const EncArgs &A, int o, PointCtx &P) 
     return true;
 }
 
-// Forward: emb[o] = mean of h2, act[o] = fraction of points with a2 > 0.
-// One wavefront per object, persistent over objects.
-__global__ __launch_bounds__(256) void enc_fwd_kernel(EncArgs A) {
+// Forward: emb[o] = mean of h2, act[o] = fraction of points with a2 > 0 (when
+// act is given).  One wavefront per object, persistent over objects.  Held to
+// two wavefronts per SIMD, which it fits without spills (unbounded, the
+// compiler keeps more in flight and allows only one).
+__global__ __launch_bounds__(256, 2) void enc_fwd_kernel(EncArgs A) {
     extern __shared__ __align__(16) unsigned char lds[];
     bf16x8 *w1f = (bf16x8 *)lds;
     bf16x8 *w2f = w1f + kW1f;
