@@ -260,3 +260,28 @@ def test_tile_size_does_not_change_results(ctx):
             np.testing.assert_array_equal(pg, pg0)
     finally:
         ctx.set_tile(0)
+
+
+def test_size_limits(ctx):
+    # the longest curve the default spans fit in LDS (3,072 points on 16x3
+    # groups) against the oracle on a few frequencies; one point more, and a
+    # curve above SS_MAX_POINTS, are reported too long with NaN rows
+    import torch
+    lens = [3072, 3073, 5000]
+    cats = [synth.make_catalog(700 + i, 1, n, 3000.0, (0.2, 10.0), 0.02, shapes=(2,))
+            for i, n in enumerate(lens)]
+    offs = np.concatenate([[0], np.cumsum([c.offsets[-1] for c in cats])]).astype(np.int64)
+    t = np.concatenate([c.t for c in cats])
+    y = np.concatenate([c.y for c in cats])
+    e = np.concatenate([c.e for c in cats])
+    grid = (0.05, 5.0, 7)
+    for method in (oracle.SS, oracle.SSSP):
+        pg, st = _gpu_pgram(ctx, method, offs, t, y, e, grid)
+        assert list(st) == [0, ssg.OBJ_TOO_LONG, ssg.OBJ_TOO_LONG]
+        assert np.isnan(pg[1:]).all()
+        po, so = oracle.periodogram(method, offs[:2], t[:3072], y[:3072], e[:3072], *grid)
+        _assert_pgram_close(pg[:1], po, what=f"n=3072 method={method}")
+        dc = ssg.DeviceCatalog.from_numpy(offs, t, y, e)
+        bi, bp, bw, st2 = ctx.ss_best_period(method, dc, grid)
+        torch.cuda.synchronize()
+        assert list(bi.cpu().numpy()[1:]) == [-1, -1]
