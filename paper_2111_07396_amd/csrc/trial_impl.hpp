@@ -35,21 +35,28 @@ __device__ __forceinline__ int phys(int u) {
     return (PPL % 2 == 0) ? u + u / PPL : u;
 }
 
+// Groups of up to 1,024 points keep the work item's object (t, y, w) in LDS
+// for all of its trials; larger groups read it from global memory per trial
+// and carry y, w through the sort.
+constexpr __host__ __device__ bool caches_object(int np) { return np <= 1024; }
+
 // LDS layout of one trial group; identical on host and device.
 struct Layout {
-    int np, ext, slots, arr, sk, xch, qslot, bytes;
+    int np, ext, slots, arr, sk, xch, qslot, obj, bytes;
     __host__ __device__ Layout(int nw, int ppl, int ext_) {
         np = kWave * nw * ppl;
         ext = ext_;
+        const bool cache = caches_object(np);
         const int ulen = np + 2 * ext + 1;
         slots = (ppl % 2 == 0) ? ulen + ulen / ppl + 1 : ulen;
         arr = (slots * 8 + 15) / 16 * 16;
-        const int sort_end = ((np + 1) * 4 + 15) / 16 * 16 + 3 * np * 8;
+        const int sort_end = ((np + 1) * 4 + 15) / 16 * 16 + (cache ? 1 : 3) * np * 8;
         int a = 3 * arr > sort_end ? 3 * arr : sort_end;
         sk = (a + 15) / 16 * 16;
         xch = sk + np * 8;
         qslot = xch + nw * 8 * 8;
-        bytes = qslot + 16;
+        obj = qslot + 16;
+        bytes = obj + (cache ? 3 * np * 8 : 0);
     }
 };
 
@@ -755,13 +762,17 @@ __device__ double run_trial(Group<P, NW, PPL> &G, unsigned char *lds, const Layo
     using R = typename P::R;
     using S = typename P::S;
     const int n = G.n, t = G.t, NP = Y.np;
+    constexpr bool kCache = caches_object(kWave * NW * PPL);
+    const double *ct = (const double *)(lds + Y.obj);  // object cache (kCache)
+    const R *cy = (const R *)(lds + Y.obj + NP * 8);
+    const R *cw = (const R *)(lds + Y.obj + 2 * NP * 8);
     // ---- fold (FP64): phase = frac(tt*f), as a 48-bit fixed-point key with
     // the point index in the low 16 bits (stable order on equal phases)
     uint64_t key[PPL];
 #pragma unroll
     for (int p = 0; p < PPL; ++p) {
         const int j = t * PPL + p;
-        const double u = od.tt[min(j, n - 1)] * f;
+        const double u = (kCache ? ct : od.tt)[min(j, n - 1)] * f;
         const double ph = u - floor(u);
         const uint64_t ph48 = (uint64_t)(ph * 0x1p48);
         key[p] = j < n ? ((ph48 << 16) | (uint64_t)j) : ~0ull;
@@ -826,8 +837,10 @@ __device__ double run_trial(Group<P, NW, PPL> &G, unsigned char *lds, const Layo
             for (uint32_t i = s; i < e; ++i) rank += tmp[i] < key[p] ? 1u : 0u;
             const uint32_t pos = s + rank;
             SK[pos] = key[p];
-            sy[pos] = od.y[j];
-            sw[pos] = od.w[j];
+            if constexpr (!kCache) {
+                sy[pos] = od.y[j];
+                sw[pos] = od.w[j];
+            }
         }
     }
     bsync<NW>();
@@ -839,8 +852,14 @@ __device__ double run_trial(Group<P, NW, PPL> &G, unsigned char *lds, const Layo
         const int j = t * PPL + p;
         const bool ok = j < n;
         const uint64_t k = ok ? SK[j] : ~0ull;
-        y[p] = ok ? sy[j] : R(0);
-        w[p] = ok ? sw[j] : R(0);
+        if constexpr (kCache) {
+            const int i = ok ? (int)(k & 0xffffu) : 0;  // original index of the sorted point
+            y[p] = ok ? cy[i] : R(0);
+            w[p] = ok ? cw[i] : R(0);
+        } else {
+            y[p] = ok ? sy[j] : R(0);
+            w[p] = ok ? sw[j] : R(0);
+        }
         x[p] = ok ? P::x_of_key(k) : P::zero();
         wx[p] = P::mulr(x[p], w[p]);
         if (j + 1 < n) tie |= (SK[j + 1] >> 16) == (k >> 16);
@@ -921,6 +940,17 @@ __device__ void run_item(Group<P, NW, PPL> &G, unsigned char *lds, const Layout 
     od.y = (P::kIsF64 ? (const R *)L.cat.yc : (const R *)L.cat.yc32) + base;
     od.w = (P::kIsF64 ? (const R *)L.cat.w : (const R *)L.cat.w32) + base;
     const double chi0 = L.cat.chi0[obj];
+    if constexpr (caches_object(kWave * NW * PPL)) {
+        double *ct = (double *)(lds + Y.obj);
+        R *cy = (R *)(lds + Y.obj + Y.np * 8);
+        R *cw = (R *)(lds + Y.obj + 2 * Y.np * 8);
+        for (int i = G.t; i < G.n; i += kWave * NW) {
+            ct[i] = od.tt[i];
+            cy[i] = od.y[i];
+            cw[i] = od.w[i];
+        }
+        bsync<NW>();
+    }
     double best_p = 0.0;
     int32_t best_k = -1;
     for (int64_t k = k0; k < k1; ++k) {
