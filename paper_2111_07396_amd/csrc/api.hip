@@ -18,19 +18,25 @@ namespace ssg {
 // precision, the fastest shape measured on MI355X for each length range
 // (synthetic catalogs; each kernel with its own register budget, see
 // trial_impl.hpp): single-wavefront groups while one wavefront holds the curve at
-// up to 3 points per thread, then two wavefronts for SS and one wavefront at
-// 4 points for the single-pass methods, wider groups above.
+// up to 3 points per thread, then two wavefronts for FP64 SS and one wavefront
+// at 4 points for the single-pass methods and compensated-FP32 SS (whose
+// pair sums need twice the registers), wider groups above.
 struct ShapeRow {
     int32_t n_max, nw, ppl;
 };
-constexpr ShapeRow kDefSS[] = {{64, 1, 1},   {128, 1, 2},  {192, 1, 3},  {256, 2, 2},
-                               {384, 2, 3},  {512, 4, 2},  {1024, 8, 2}, {2048, 8, 4},
-                               {3072, 16, 3}, {4096, 16, 4}};
+constexpr ShapeRow kDefSS64[] = {{64, 1, 1},   {128, 1, 2},  {192, 1, 3},  {256, 2, 2},
+                                 {384, 4, 2},  {512, 4, 2},  {1024, 8, 2}, {2048, 8, 4},
+                                 {3072, 16, 3}, {4096, 16, 4}};
+constexpr ShapeRow kDefSS32[] = {{64, 1, 1},   {128, 1, 2},  {192, 1, 3},  {256, 1, 4},
+                                 {384, 2, 3},  {512, 4, 2},  {1024, 4, 4}, {2048, 8, 4},
+                                 {3072, 16, 3}, {4096, 16, 4}};
 constexpr ShapeRow kDefSP[] = {{64, 1, 1},   {128, 1, 2},  {192, 1, 3},  {256, 1, 4},
                                {384, 2, 3},  {512, 4, 2},  {1024, 4, 4}, {2048, 8, 4},
                                {3072, 16, 3}, {4096, 16, 4}};
-constexpr int kNumDefRows = (int)(sizeof(kDefSS) / sizeof(kDefSS[0]));
-static_assert(kNumDefRows == (int)(sizeof(kDefSP) / sizeof(kDefSP[0])), "tables");
+constexpr int kNumDefRows = (int)(sizeof(kDefSP) / sizeof(kDefSP[0]));
+static_assert(kNumDefRows == (int)(sizeof(kDefSS64) / sizeof(kDefSS64[0])) &&
+                  kNumDefRows == (int)(sizeof(kDefSS32) / sizeof(kDefSS32[0])),
+              "tables");
 
 int shape_index(int nw, int ppl) {
     for (int s = 0; s < kNumShapes; ++s)
@@ -38,8 +44,9 @@ int shape_index(int nw, int ppl) {
     return -1;
 }
 
-const ShapeRow *default_rows(int method, int /*precision*/) {
-    return method == 0 ? kDefSS : kDefSP;
+const ShapeRow *default_rows(int method, int precision) {
+    if (method != 0) return kDefSP;
+    return precision == SS_FP64 ? kDefSS64 : kDefSS32;
 }
 
 }  // namespace ssg

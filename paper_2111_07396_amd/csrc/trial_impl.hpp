@@ -165,11 +165,20 @@ __device__ __forceinline__ void group_excl(const Group<P, NW, PPL> &G,
 
 // Exclusive prefix sums P[i] = sum_{j<i} v_j of M quantities at slots
 // 0..n (padding points contribute 0); returns the totals.  Ends with a sync.
-template <class P, int NW, int PPL, int M>
+// EXT: the arrays are the x-moment prefix (W, X, XX; M = 3) or a prefix pair
+// (V, XV of w v and w x v; M = 2), and their periodic extension by e slots
+// per side is written with them: each thread writes the copies of its own
+// prefix values (every thread holds the totals after the group scan).
+//   right: P(n+k) = T + P(k)   with the copy's phase shifted by +1,
+//   left:  P(-k) = P(n-k) - T  with the copy's phase shifted by -1,
+// so that X and XX pick up the terms of (x +- 1) and (x +- 1)^2.  Slots past
+// n + e are left unwritten (no window reaches them).
+template <class P, int NW, int PPL, int M, bool EXT>
 __device__ __forceinline__ void build_prefix(const Group<P, NW, PPL> &G,
                                              typename P::S *const (&Pf)[M],
                                              const typename P::S (&v)[M][PPL],
-                                             typename P::S (&T)[M]) {
+                                             typename P::S (&T)[M], int e = 0) {
+    static_assert(!EXT || M == 2 || M == 3, "extension of a pair or of the x-moments");
     using S = typename P::S;
     S loc[M][PPL], tot[M], excl[M];
 #pragma unroll
@@ -184,11 +193,50 @@ __device__ __forceinline__ void build_prefix(const Group<P, NW, PPL> &G,
         tot[m] = acc;
     }
     group_excl<P, NW, PPL, M>(G, tot, excl, T);
+    const int n = G.n;
 #pragma unroll
-    for (int m = 0; m < M; ++m) {
+    for (int p = 0; p < PPL; ++p) {
+        const int u = G.t * PPL + p + 1;
+        S val[M];
 #pragma unroll
-        for (int p = 0; p < PPL; ++p) Pf[m][G.slot(G.t * PPL + p + 1)] = P::add(excl[m], loc[m][p]);
-        if (G.t == 0) Pf[m][G.slot(0)] = P::zero();
+        for (int m = 0; m < M; ++m) val[m] = P::add(excl[m], loc[m][p]);
+        if (!EXT || u <= n) {
+#pragma unroll
+            for (int m = 0; m < M; ++m) Pf[m][G.slot(u)] = val[m];
+        }
+        if constexpr (EXT) {
+            if (u <= e && u <= n) {  // right copy, k = u
+                const int d = G.slot(n + u);
+                if constexpr (M == 3) {
+                    Pf[0][d] = P::add(T[0], val[0]);
+                    Pf[1][d] = P::add(P::add(T[1], val[1]), val[0]);
+                    Pf[2][d] = P::add(P::add(T[2], val[2]), P::add(P::twice(val[1]), val[0]));
+                } else {
+                    Pf[0][d] = P::add(T[0], val[0]);
+                    Pf[1][d] = P::add(P::add(T[1], val[1]), val[0]);
+                }
+            }
+            if (u < n && u >= n - e) {  // left copy, k = n - u
+                const int d = G.slot(u - n);
+                if constexpr (M == 3) {
+                    const S rw = P::sub(T[0], val[0]);
+                    const S rx = P::sub(T[1], val[1]);
+                    const S rxx = P::sub(T[2], val[2]);
+                    Pf[0][d] = P::neg(rw);
+                    Pf[1][d] = P::sub(rw, rx);
+                    Pf[2][d] = P::neg(P::add(P::sub(rxx, P::twice(rx)), rw));
+                } else {
+                    const S rv = P::sub(T[0], val[0]);
+                    const S rxv = P::sub(T[1], val[1]);
+                    Pf[0][d] = P::neg(rv);
+                    Pf[1][d] = P::sub(rv, rxv);
+                }
+            }
+        }
+    }
+    if (G.t == 0) {
+#pragma unroll
+        for (int m = 0; m < M; ++m) Pf[m][G.slot(0)] = P::zero();
     }
     bsync<NW>();
 }
@@ -247,6 +295,19 @@ __device__ __forceinline__ void extend2(const Group<P, NW, PPL> &G, typename P::
     bsync<NW>();
 }
 
+// Whether a kernel writes the periodic extension inside the prefix build
+// (one barrier less per prefix pass, a few more live registers) or in a
+// separate pass (extend3 / extend2).  Measured on MI355X per shape (FP64):
+// the fused form wins for one point per thread (up to 20 %) and for groups
+// of several wavefronts at two points per thread (5-10 %); with more points
+// per thread it raises the register peak and loses (up to 39 %).  The
+// compensated-FP32 kernels, with twice the registers per sum, keep the
+// separate pass.
+template <bool F64, int NW, int PPL>
+constexpr bool fused_extension() {
+    return F64 && (PPL == 1 || (PPL == 2 && NW > 1));
+}
+
 // Prefix pair of w v and w x v into (A0, A1), extended by e.
 template <class P, int NW, int PPL>
 __device__ __forceinline__ void prefix_pair(const Group<P, NW, PPL> &G,
@@ -263,8 +324,12 @@ __device__ __forceinline__ void prefix_pair(const Group<P, NW, PPL> &G,
     S *const Pf[2] = {G.A0, G.A1};
     S T[2];
     bsync<NW>();
-    build_prefix<P, NW, PPL, 2>(G, Pf, q, T);
-    extend2<P, NW, PPL>(G, G.A0, G.A1, T, e);
+    if constexpr (fused_extension<P::kIsF64, NW, PPL>()) {
+        build_prefix<P, NW, PPL, 2, true>(G, Pf, q, T, e);
+    } else {
+        build_prefix<P, NW, PPL, 2, false>(G, Pf, q, T);
+        extend2<P, NW, PPL>(G, G.A0, G.A1, T, e);
+    }
 }
 
 template <class P, int NW, int PPL>
@@ -448,8 +513,12 @@ __device__ __forceinline__ void prefix_x(const Group<P, NW, PPL> &G,
     S *const Pf[3] = {G.A0, G.A1, G.A2};
     S T[3];
     bsync<NW>();
-    build_prefix<P, NW, PPL, 3>(G, Pf, q, T);
-    extend3<P, NW, PPL>(G, G.A0, G.A1, G.A2, T, e);
+    if constexpr (fused_extension<P::kIsF64, NW, PPL>()) {
+        build_prefix<P, NW, PPL, 3, true>(G, Pf, q, T, e);
+    } else {
+        build_prefix<P, NW, PPL, 3, false>(G, Pf, q, T);
+        extend3<P, NW, PPL>(G, G.A0, G.A1, G.A2, T, e);
+    }
 }
 
 // ------------------------------------------------------------------ Listing 1
@@ -728,7 +797,7 @@ __device__ double pdm_score(const Group<P, NW, PPL> &G, int B, const typename P:
     S *const Pf[2] = {G.A0, G.A1};
     S T[2];
     bsync<NW>();
-    build_prefix<P, NW, PPL, 2>(G, Pf, q, T);
+    build_prefix<P, NW, PPL, 2, false>(G, Pf, q, T);
     const int n = G.n;
     const uint64_t one = 1ull << 48;
     double e = 0.0, z = 0.0;
@@ -983,13 +1052,13 @@ __device__ void run_item(Group<P, NW, PPL> &G, unsigned char *lds, const Layout 
 template <bool F64, int NW, int PPL, int METHOD>
 constexpr int waves_per_simd() {
     constexpr bool ss = METHOD == 0;
-    if (NW == 1 && PPL == 1) return (F64 && ss) ? 3 : 1;
+    if (NW == 1 && PPL == 1) return F64 ? (ss ? 4 : 1) : 1;
     if (NW == 1 && PPL == 2) return ss ? 1 : 3;
     if (NW == 1 && PPL == 3) return (F64 && ss) ? 2 : 1;
     if (NW == 1 && PPL == 4) return ss ? 1 : 2;
-    if (NW == 2 && PPL == 1) return ss ? 3 : 1;
+    if (NW == 2 && PPL == 1) return F64 ? 4 : (ss ? 3 : 1);
     if (NW == 2 && PPL == 2) return ss ? (F64 ? 2 : 1) : 3;
-    if (NW == 4 && PPL == 1) return ss ? 3 : 1;
+    if (NW == 4 && PPL == 1) return F64 ? 4 : (ss ? 3 : 1);
     if (NW == 2 && PPL == 3) return 1;  // FP64 SS held to 2 spilled to scratch and miscomputed
     if (NW == 4 && PPL == 2) return ss ? (F64 ? 2 : 1) : 3;
     if (NW == 4 && PPL == 4) return ss ? 1 : 2;
