@@ -179,7 +179,7 @@ int prepare(ss_ctx *ctx, int method, const ss_catalog *cat, const ss_params *prm
     for (int c = 0; c < kNumShapes; ++c) {
         const int np = 64 * kShapes[c].nw * kShapes[c].ppl;
         P.ext[c] = std::max(2, trial_halfwidth(np, span_hi));
-        if (trial_lds_bytes(kShapes[c].nw, kShapes[c].ppl, P.ext[c]) <= ctx->max_lds)
+        if (trial_lds_bytes(kShapes[c].nw, kShapes[c].ppl, P.ext[c], method) <= ctx->max_lds)
             R.runnable |= 1u << c;
     }
     R.fallback = shape_index(1, 1);

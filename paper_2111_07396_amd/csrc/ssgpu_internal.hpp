@@ -81,7 +81,7 @@ constexpr ShapeInfo kShapes[] = {
 };
 constexpr int kNumShapes = (int)(sizeof(kShapes) / sizeof(kShapes[0]));
 
-int trial_lds_bytes(int nw, int ppl, int ext);   // dynamic LDS of one trial group
+int trial_lds_bytes(int nw, int ppl, int ext, int method);  // dynamic LDS of one trial group
 int trial_halfwidth(int n, double span);         // window half-width b(n, span)
 
 // Shape selection on the device: the first rule with n <= n_max, else the

@@ -7,7 +7,9 @@ namespace ssg {
 hipError_t launch_trials_f32c(int shape, const TrialLaunch &L, int64_t max_items, int n_cu,
                               hipStream_t s);
 
-int trial_lds_bytes(int nw, int ppl, int ext) { return Layout(nw, ppl, ext).bytes; }
+int trial_lds_bytes(int nw, int ppl, int ext, int method) {
+    return Layout(nw, ppl, ext, method).bytes;
+}
 
 int trial_halfwidth(int n, double span) { return halfwidth(n, span); }
 

@@ -40,10 +40,24 @@ __device__ __forceinline__ int phys(int u) {
 // and carry y, w through the sort.
 constexpr __host__ __device__ bool caches_object(int np) { return np <= 1024; }
 
+// Prefix arrays of a trial group.  The SS kernels of multi-wavefront groups
+// that cache the object alternate their later smooths between two prefix
+// pairs, (A0, A1) and (A2, A3): a pass then needs no barrier before it
+// writes, as the pair it overwrites was last read two passes earlier, behind
+// that pass's barriers (measured: +3-7 % on these kernels; a single
+// wavefront's barrier is only a wait on its own LDS operations, and there the
+// change lost up to 9 %).
+constexpr __host__ __device__ bool double_buffered(int method, int nw, int ppl) {
+    return method == 0 && nw > 1 && caches_object(kWave * nw * ppl);
+}
+constexpr __host__ __device__ int prefix_arrays(int method, int nw, int ppl) {
+    return double_buffered(method, nw, ppl) ? 4 : 3;
+}
+
 // LDS layout of one trial group; identical on host and device.
 struct Layout {
     int np, ext, slots, arr, sk, xch, qslot, obj, bytes;
-    __host__ __device__ Layout(int nw, int ppl, int ext_) {
+    __host__ __device__ Layout(int nw, int ppl, int ext_, int method) {
         np = kWave * nw * ppl;
         ext = ext_;
         const bool cache = caches_object(np);
@@ -51,7 +65,8 @@ struct Layout {
         slots = (ppl % 2 == 0) ? ulen + ulen / ppl + 1 : ulen;
         arr = (slots * 8 + 15) / 16 * 16;
         const int sort_end = ((np + 1) * 4 + 15) / 16 * 16 + (cache ? 1 : 3) * np * 8;
-        int a = 3 * arr > sort_end ? 3 * arr : sort_end;
+        const int narr = prefix_arrays(method, nw, ppl);
+        int a = narr * arr > sort_end ? narr * arr : sort_end;
         sk = (a + 15) / 16 * 16;
         xch = sk + np * 8;
         qslot = xch + nw * 8 * 8;
@@ -74,6 +89,7 @@ struct Group {
     using S = typename P::S;
     static constexpr int NT = kWave * NW;
     S *A0, *A1, *A2;         // prefix arrays (or scratch)
+    S *A3;                   // second pair's second array (double-buffered SS)
     const uint64_t *SK;      // sorted keys
     S *xs;                   // exchange slots for group scans
     double *xd;              // exchange slots for group sums
@@ -308,8 +324,10 @@ constexpr bool fused_extension() {
     return F64 && (PPL == 1 || (PPL == 2 && NW > 1));
 }
 
-// Prefix pair of w v and w x v into (A0, A1), extended by e.
-template <class P, int NW, int PPL>
+// Prefix pair of w v and w x v, extended by e.  BUF 0: into (A0, A1) after a
+// barrier; BUF 1: into (A2, A3), BUF 2: into (A0, A1), both without one
+// (double-buffered passes).
+template <class P, int NW, int PPL, int BUF = 0>
 __device__ __forceinline__ void prefix_pair(const Group<P, NW, PPL> &G,
                                             const typename P::R (&w)[PPL],
                                             const typename P::S (&wx)[PPL],
@@ -321,14 +339,16 @@ __device__ __forceinline__ void prefix_pair(const Group<P, NW, PPL> &G,
         q[0][p] = P::prod(w[p], v[p]);
         q[1][p] = P::mulr(wx[p], v[p]);
     }
-    S *const Pf[2] = {G.A0, G.A1};
+    S *const V = BUF == 1 ? G.A2 : G.A0;
+    S *const XV = BUF == 1 ? G.A3 : G.A1;
+    S *const Pf[2] = {V, XV};
     S T[2];
-    bsync<NW>();
+    if constexpr (BUF == 0) bsync<NW>();
     if constexpr (fused_extension<P::kIsF64, NW, PPL>()) {
         build_prefix<P, NW, PPL, 2, true>(G, Pf, q, T, e);
     } else {
         build_prefix<P, NW, PPL, 2, false>(G, Pf, q, T);
-        extend2<P, NW, PPL>(G, G.A0, G.A1, T, e);
+        extend2<P, NW, PPL>(G, V, XV, T, e);
     }
 }
 
@@ -449,6 +469,24 @@ __device__ void cv_fallback(const Group<P, NW, PPL> &G, bool any, typename P::R 
     bsync<NW>();
 }
 
+// Whether any point has a negative (marked) residual in any of three arrays.
+template <class P, int NW, int PPL>
+__device__ __forceinline__ bool group_any_neg3(const Group<P, NW, PPL> &G,
+                                               const typename P::R (&r0)[PPL],
+                                               const typename P::R (&r1)[PPL],
+                                               const typename P::R (&r2)[PPL]) {
+    using R = typename P::R;
+    bool bad = false;
+#pragma unroll
+    for (int p = 0; p < PPL; ++p)
+        bad |= (G.t * PPL + p < G.n) && (r0[p] < R(0) || r1[p] < R(0) || r2[p] < R(0));
+    if constexpr (NW == 1) {
+        return wave_ballot(bad) != 0;
+    } else {
+        return __syncthreads_or(bad) != 0;
+    }
+}
+
 // Whether any point of the group has a negative (marked) residual.
 template <class P, int NW, int PPL>
 __device__ __forceinline__ bool group_any_neg(const Group<P, NW, PPL> &G,
@@ -482,17 +520,24 @@ __device__ __forceinline__ double chi2_of(const Group<P, NW, PPL> &G,
     return a;
 }
 
-// Smooth of v with a stored geometry (phase B): prefix pair, fit, ties.
-template <class P, int NW, int PPL>
+// Smooth of v with a stored geometry (phase B): prefix pair (BUF as in
+// prefix_pair), fit, ties.
+template <class P, int NW, int PPL, int BUF = 0>
 __device__ __forceinline__ void smooth_with(const Group<P, NW, PPL> &G, int b,
                                            const typename P::Geo (&g)[PPL],
                                            const typename P::R (&w)[PPL],
                                            const typename P::S (&wx)[PPL],
                                            const typename P::R (&v)[PPL], int e,
                                            typename P::R (&s)[PPL]) {
-    prefix_pair<P, NW, PPL>(G, w, wx, v, e);
+    prefix_pair<P, NW, PPL, BUF>(G, w, wx, v, e);
+    const typename P::S *V = BUF == 1 ? G.A2 : G.A0;
+    const typename P::S *XV = BUF == 1 ? G.A3 : G.A1;
 #pragma unroll
-    for (int p = 0; p < PPL; ++p) s[p] = window_fit<P, NW, PPL>(G, g[p], min(G.t * PPL + p, G.n - 1), b);
+    for (int p = 0; p < PPL; ++p) {
+        const int j = min(G.t * PPL + p, G.n - 1);
+        const int hi = G.slot(j + b + 1), lo = G.slot(j - b);
+        s[p] = P::eval(g[p], P::sub(V[hi], V[lo]), P::sub(XV[hi], XV[lo]));
+    }
     if (G.ties) tie_average<P, NW, PPL>(G, w, s);
 }
 
@@ -571,9 +616,19 @@ __device__ double supersmoother(const Group<P, NW, PPL> &G, const TrialLaunch &L
         r2[p] = cv_resid<P>(y[p], s2[p], w[p], h2[p]);
     }
     // ---- phase B: fallbacks and ties of the primaries
-    cv_fallback<P, NW, PPL>(G, group_any_neg<P, NW, PPL>(G, r0), r0);
-    cv_fallback<P, NW, PPL>(G, group_any_neg<P, NW, PPL>(G, r1), r1);
-    cv_fallback<P, NW, PPL>(G, group_any_neg<P, NW, PPL>(G, r2), r2);
+    constexpr bool kDB = double_buffered(0, NW, PPL);
+    if constexpr (kDB) {
+        // one group vote for the three residual arrays (a fallback leaves an
+        // array without marked residuals unchanged)
+        const bool any_neg = group_any_neg3<P, NW, PPL>(G, r0, r1, r2);
+        cv_fallback<P, NW, PPL>(G, any_neg, r0);
+        cv_fallback<P, NW, PPL>(G, any_neg, r1);
+        cv_fallback<P, NW, PPL>(G, any_neg, r2);
+    } else {
+        cv_fallback<P, NW, PPL>(G, group_any_neg<P, NW, PPL>(G, r0), r0);
+        cv_fallback<P, NW, PPL>(G, group_any_neg<P, NW, PPL>(G, r1), r1);
+        cv_fallback<P, NW, PPL>(G, group_any_neg<P, NW, PPL>(G, r2), r2);
+    }
     if (G.ties) {
         tie_average<P, NW, PPL>(G, w, s0);
         tie_average<P, NW, PPL>(G, w, s1);
@@ -582,23 +637,25 @@ __device__ double supersmoother(const Group<P, NW, PPL> &G, const TrialLaunch &L
     // midrange smooths of the residuals; per-point span choice, the lowest
     // span winning ties (Listing 1 scans the spans upward with a strict <,
     // starting from 1e20; the span stays 0 if no residual is below that)
+    // (double-buffered groups alternate the prefix pairs of these passes)
+    constexpr int kB1 = kDB ? 1 : 0, kB2 = kDB ? 2 : 0;
     const int eb = b1 > b0 ? b1 : b0;
     R resmin[PPL], sel[PPL], rt[PPL];
-    smooth_with<P, NW, PPL>(G, b1, g1, w, wx, r0, eb, rt);
+    smooth_with<P, NW, PPL, kB1>(G, b1, g1, w, wx, r0, eb, rt);
 #pragma unroll
     for (int p = 0; p < PPL; ++p) {
         const bool lt = rt[p] < R(1.0e20);
         resmin[p] = lt ? rt[p] : R(1.0e20);
         sel[p] = lt ? sp0 : R(0);
     }
-    smooth_with<P, NW, PPL>(G, b1, g1, w, wx, r1, eb, rt);
+    smooth_with<P, NW, PPL, kB2>(G, b1, g1, w, wx, r1, eb, rt);
 #pragma unroll
     for (int p = 0; p < PPL; ++p) {
         const bool lt = rt[p] < resmin[p];
         resmin[p] = lt ? rt[p] : resmin[p];
         sel[p] = lt ? sp1 : sel[p];
     }
-    smooth_with<P, NW, PPL>(G, b1, g1, w, wx, r2, eb, rt);
+    smooth_with<P, NW, PPL, kB1>(G, b1, g1, w, wx, r2, eb, rt);
 #pragma unroll
     for (int p = 0; p < PPL; ++p) {
         const bool lt = rt[p] < resmin[p];
@@ -619,7 +676,7 @@ __device__ double supersmoother(const Group<P, NW, PPL> &G, const TrialLaunch &L
         }
     }
     // midrange smooth of the chosen spans, clip, blend
-    smooth_with<P, NW, PPL>(G, b1, g1, w, wx, sel, eb, rt);
+    smooth_with<P, NW, PPL, kB2>(G, b1, g1, w, wx, sel, eb, rt);
     const R ilo = R(1) / (sp0 - sp1), ihi = R(1) / (sp2 - sp1);
 #pragma unroll
     for (int p = 0; p < PPL; ++p) {
@@ -633,7 +690,7 @@ __device__ double supersmoother(const Group<P, NW, PPL> &G, const TrialLaunch &L
     }
     // tweeter smooth of the blend
     R smo[PPL];
-    smooth_with<P, NW, PPL>(G, b0, g0, w, wx, rt, eb, smo);
+    smooth_with<P, NW, PPL, kB1>(G, b0, g0, w, wx, rt, eb, smo);
     return chi2_of<P, NW, PPL>(G, w, y, smo);
 }
 
@@ -1074,11 +1131,12 @@ __global__ __launch_bounds__(kWave *NW,
 void trial_kernel(TrialLaunch L) {
     using S = typename P::S;
     extern __shared__ __align__(16) unsigned char lds[];
-    const Layout Y(NW, PPL, L.ext);
+    const Layout Y(NW, PPL, L.ext, METHOD);
     Group<P, NW, PPL> G;
     G.A0 = (S *)lds;
     G.A1 = (S *)(lds + Y.arr);
     G.A2 = (S *)(lds + 2 * Y.arr);
+    G.A3 = (S *)(lds + 3 * Y.arr);  // used only where the layout has a fourth array
     G.SK = (const uint64_t *)(lds + Y.sk);
     G.xs = (S *)(lds + Y.xch);
     G.xd = (double *)(lds + Y.xch);
@@ -1103,7 +1161,7 @@ void trial_kernel(TrialLaunch L) {
 
 template <class P, int NW, int PPL, int METHOD, bool PDM>
 hipError_t launch_variant(const TrialLaunch &L, int64_t max_items, int n_cu, hipStream_t s) {
-    const Layout Y(NW, PPL, L.ext);
+    const Layout Y(NW, PPL, L.ext, METHOD);
     const void *fn = (const void *)trial_kernel<P, NW, PPL, METHOD, PDM>;
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, Y.bytes);
     if (e != hipSuccess) return e;
