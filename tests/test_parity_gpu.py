@@ -285,3 +285,35 @@ def test_size_limits(ctx):
         bi, bp, bw, st2 = ctx.ss_best_period(method, dc, grid)
         torch.cuda.synchronize()
         assert list(bi.cpu().numpy()[1:]) == [-1, -1]
+
+
+@pytest.mark.parametrize("method", [oracle.SS, oracle.SSSP, oracle.SSSP2])
+def test_ties_and_uneven_weights_on_every_shape(ctx, method):
+    # tie averaging on every group shape, forced for the light curve (exact
+    # phase ties from dyadic times at power-of-two frequencies), and eight
+    # points whose weights span four decades on every shape (almost all of a
+    # group's slots are padding)
+    rng = np.random.default_rng(77)
+    tie_t = np.sort(rng.choice(2048, 60, replace=False)) / 16.0
+    tie_y = 15 + 0.2 * np.sin(2 * np.pi * tie_t / 3.0) + rng.normal(0, 0.05, tie_t.size)
+    tie_e = rng.uniform(0.03, 0.08, tie_t.size)
+    fb_t = np.array([0.0, 0.31, 0.77, 1.2, 2.9, 3.3, 5.05, 7.4])
+    fb_y = np.array([15.0, 15.4, 14.8, 15.2, 15.1, 14.7, 15.3, 15.0])
+    fb_e = np.array([0.001, 0.2, 0.3, 0.002, 0.25, 0.1, 0.003, 0.3])
+    cases = [("ties", tie_t, tie_y, tie_e, [(f, 2 * f, 1) for f in (0.25, 1.0, 4.0)]),
+             ("uneven weights", fb_t, fb_y, fb_e, [(0.05, 3.0, 41)])]
+    try:
+        for name, t, y, e, grids in cases:
+            offs = np.array([0, t.size], dtype=np.int64)
+            for nw, ppl in ssg.shapes():
+                ctx.set_shape(0, 0, 0)
+                ctx.set_shape(t.size, nw, ppl)
+                for grid in grids:
+                    po, so = oracle.periodogram(method, offs, t, y, e, *grid)
+                    pg, sg = _gpu_pgram(ctx, method, offs, t, y, e, grid)
+                    if (sg == ssg.OBJ_TOO_LONG).all():
+                        continue
+                    assert np.array_equal(so, sg)
+                    _assert_pgram_close(pg, po, what=f"{name} {nw}x{ppl} grid={grid}")
+    finally:
+        ctx.set_shape(0, 0, 0)
