@@ -23,6 +23,7 @@ from __future__ import annotations
 
 import argparse
 import hashlib
+import re
 import json
 import os
 import sys
@@ -41,17 +42,26 @@ PEAK_VALU_TFLOPS = 78.6
 ENCODER_WEIGHTS = os.path.join(ROOT, "paper_2111_07396_amd", "weights", "encoder_c5.npy")
 
 
-def _src_hash() -> str:
-    """Hash of the sources the trial kernel is built from (its own file, the
+def _code_only(src: bytes) -> bytes:
+    """C++ source without comments, whitespace runs collapsed (so that an edit
+    of a comment does not count as a change of the kernel)."""
+    src = re.sub(rb"/\*.*?\*/", b" ", src, flags=re.S)
+    src = re.sub(rb"//[^\n]*", b" ", src)
+    return b" ".join(src.split())
+
+
+def _src_hash(csrc: str = "") -> str:
+    """Hash of the code the trial kernel is built from (its own file, the
     arithmetic and wavefront helpers, and the launch structures that precede
-    the learned-proposal declarations in the internal header)."""
-    csrc = os.path.join(ROOT, "paper_2111_07396_amd", "csrc")
+    the learned-proposal declarations in the internal header), comments and
+    layout ignored."""
+    csrc = csrc or os.path.join(ROOT, "paper_2111_07396_amd", "csrc")
     h = hashlib.sha256()
     for name in ("trial_impl.hpp", "trial_f64.hip", "trial_f32c.hip", "numeric.hpp", "wave.hpp"):
         with open(os.path.join(csrc, name), "rb") as f:
-            h.update(f.read())
+            h.update(_code_only(f.read()))
     with open(os.path.join(csrc, "ssgpu_internal.hpp"), "rb") as f:
-        h.update(f.read().split(b"// ---- learned frequency proposal")[0])
+        h.update(_code_only(f.read().split(b"// ---- learned frequency proposal")[0]))
     return h.hexdigest()[:16]
 
 

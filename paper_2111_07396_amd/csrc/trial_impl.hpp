@@ -18,9 +18,10 @@
 //   phase A1: prefix of w, w x, w x^2 -> geometry of every span;
 //   phase A2: prefix of w y, w x y    -> the cross-validated smooths of y;
 //   phase B:  one prefix pair per later smooth (residuals, spans, blend).
-// Only three prefix arrays are live at any time.  With PPL even, the arrays
-// get one pad slot per PPL slots so that the threads' reads at a common
-// offset fall in distinct LDS banks.
+// Three prefix arrays are live at a time (four where the phase-B pairs are
+// double-buffered, see double_buffered).  With PPL even, the arrays get one
+// pad slot per PPL slots so that the threads' reads at a common offset fall
+// in distinct LDS banks.
 #pragma once
 #include "numeric.hpp"
 #include "ssgpu_internal.hpp"
