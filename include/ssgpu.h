@@ -71,7 +71,10 @@ extern "C" {
                                largest span, clip and blend as in Listing 1, chi^2 of
                                the blend (no residual, span or final smooth) */
 
-/* Largest light curve the library accepts (points per object). */
+/* Largest light curve the library accepts (points per object).  On MI355X
+ * (160 KB of LDS per workgroup) a trial group for more than 3,072 points does not
+ * fit at any span_max >= 0.1, so such objects are reported SS_OBJ_TOO_LONG; up to
+ * 3,072 points run at the default spans. */
 #define SS_MAX_POINTS 4096
 
 typedef struct ss_ctx ss_ctx;
