@@ -85,3 +85,23 @@ def test_bench_refuses_more_than_one_gpu():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_bench_source_hash_ignores_comments_but_not_code(tmp_path):
+    # the committed traffic counters are keyed to the trial-kernel code: a
+    # comment or layout edit keeps the key, any code edit changes it
+    import shutil
+    sys.path.insert(0, ROOT)
+    import bench
+    csrc = os.path.join(ROOT, "paper_2111_07396_amd", "csrc")
+    for name in ("trial_impl.hpp", "trial_f64.hip", "trial_f32c.hip", "numeric.hpp", "wave.hpp",
+                 "ssgpu_internal.hpp"):
+        shutil.copy(os.path.join(csrc, name), tmp_path / name)
+    h0 = bench._src_hash(str(tmp_path))
+    assert h0 == bench._src_hash()
+    src = (tmp_path / "trial_impl.hpp").read_text()
+    (tmp_path / "trial_impl.hpp").write_text(
+        "// a new comment line\n" + src.replace("#pragma once", "#pragma once   /* note */"))
+    assert bench._src_hash(str(tmp_path)) == h0
+    (tmp_path / "trial_impl.hpp").write_text(src.replace("np <= 1024", "np <= 512", 1))
+    assert bench._src_hash(str(tmp_path)) != h0
