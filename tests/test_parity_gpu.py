@@ -287,8 +287,9 @@ def test_size_limits(ctx):
         assert list(bi.cpu().numpy()[1:]) == [-1, -1]
 
 
+@pytest.mark.parametrize("precision", [ssg.SS_FP64, ssg.SS_FP32C])
 @pytest.mark.parametrize("method", [oracle.SS, oracle.SSSP, oracle.SSSP2])
-def test_ties_and_uneven_weights_on_every_shape(ctx, method):
+def test_ties_and_uneven_weights_on_every_shape(ctx, method, precision):
     # tie averaging on every group shape, forced for the light curve (exact
     # phase ties from dyadic times at power-of-two frequencies), and eight
     # points whose weights span four decades on every shape (almost all of a
@@ -310,10 +311,12 @@ def test_ties_and_uneven_weights_on_every_shape(ctx, method):
                 ctx.set_shape(t.size, nw, ppl)
                 for grid in grids:
                     po, so = oracle.periodogram(method, offs, t, y, e, *grid)
-                    pg, sg = _gpu_pgram(ctx, method, offs, t, y, e, grid)
+                    pg, sg = _gpu_pgram(ctx, method, offs, t, y, e, grid,
+                                        ssg.Params(precision=precision))
                     if (sg == ssg.OBJ_TOO_LONG).all():
                         continue
                     assert np.array_equal(so, sg)
-                    _assert_pgram_close(pg, po, what=f"{name} {nw}x{ppl} grid={grid}")
+                    _assert_pgram_close(pg, po, tol=TOL if precision == ssg.SS_FP64 else 1e-2,
+                                        what=f"{name} {nw}x{ppl} grid={grid}")
     finally:
         ctx.set_shape(0, 0, 0)
