@@ -14,12 +14,14 @@
 
 namespace ssg {
 
-// 1/a for FP64: hardware estimate refined by two Newton steps (about one ulp).
+// 1/a for FP64: the hardware estimate (about 2^-23 relative on gfx950) refined
+// by one Newton step, r' = r + r (1 - a r), which squares the relative error:
+// measured on 4M log-uniform values over 2^-30..2^30, at most 11 ulp from the
+// correctly rounded quotient (a second step makes it exact there, for 2 more
+// FMA per reciprocal; 11 ulp is far below the window sums' own rounding).
 __device__ __forceinline__ double rcp64(double a) {
-    double r = __builtin_amdgcn_rcp(a);
-    double e = fma(-a, r, 1.0);
-    r = fma(e, r, r);
-    e = fma(-a, r, 1.0);
+    const double r = __builtin_amdgcn_rcp(a);
+    const double e = fma(-a, r, 1.0);
     return fma(e, r, r);
 }
 
