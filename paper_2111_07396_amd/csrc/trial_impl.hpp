@@ -96,6 +96,7 @@ struct Group {
     double *xd;              // exchange slots for group sums
     int t, wave, lane, n, ext;
     double vsmlsq;
+    double inv_n, inv_chi0;  // 1/n and 1/chi0 of the work item's object
     bool ties;
     __device__ int slot(int i) const { return phys<PPL>(ext + i); }
 };
@@ -670,7 +671,7 @@ __device__ double supersmoother(const Group<P, NW, PPL> &G, const TrialLaunch &L
 #pragma unroll
         for (int p = 0; p < PPL; ++p) {
             if (resmin[p] < rt[p] && resmin[p] > R(0)) {
-                R tmp = resmin[p] / rt[p];
+                R tmp = resmin[p] * P::rcp(rt[p]);
                 if (tmp < R(1.0e-7)) tmp = R(1.0e-7);
                 sel[p] += (sp2 - sel[p]) * bass_pow<P>(tmp, ex);
             }
@@ -754,8 +755,9 @@ __device__ double single_pass(const Group<P, NW, PPL> &G, const TrialLaunch &L,
             R iden[3];
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
-                ok[k] = trd[k] < (double)n;
-                iden[k] = ok[k] ? (R)(1.0 / (1.0 - trd[k] / (double)n)) : R(0);
+                const double den = 1.0 - trd[k] * G.inv_n;  // > 0 whenever TR_k < n
+                ok[k] = trd[k] < (double)n && den > 0.0;
+                iden[k] = ok[k] ? (R)rcp64(den) : R(0);
             }
             const R sp0 = (R)L.span[0], sp1 = (R)L.span[1], sp2 = (R)L.span[2];
             const R spk[3] = {sp0, sp1, sp2};
@@ -811,10 +813,8 @@ __device__ double single_pass(const Group<P, NW, PPL> &G, const TrialLaunch &L,
         double rss_d = P::dbl(rss), tr_d = P::dbl(tr[k]);
         group_sum2<P, NW, PPL>(G, rss_d, tr_d);
         double gcv = __builtin_inf();
-        if (tr_d < (double)n) {
-            const double den = 1.0 - tr_d / (double)n;
-            gcv = rss_d / (den * den);
-        }
+        const double den = 1.0 - tr_d * G.inv_n;
+        if (tr_d < (double)n && den * den > 0.0) gcv = rss_d * rcp64(den * den);
         if (k == 0 || gcv < best) {
             best = gcv;
             chi2 = rss_d;
@@ -1014,7 +1014,7 @@ __device__ double run_trial(Group<P, NW, PPL> &G, unsigned char *lds, const Layo
         R smo[PPL];
 #pragma unroll
         for (int p = 0; p < PPL; ++p) smo[p] = m;
-        return 1.0 - chi2_of<P, NW, PPL>(G, w, y, smo) / chi0;
+        return 1.0 - chi2_of<P, NW, PPL>(G, w, y, smo) * G.inv_chi0;
     }
     {
         const int q = n / 4;
@@ -1024,7 +1024,7 @@ __device__ double run_trial(Group<P, NW, PPL> &G, unsigned char *lds, const Layo
     }
     const double chi2 = (METHOD == 0) ? supersmoother<P, NW, PPL>(G, L, x, w, wx, y)
                                       : single_pass<P, NW, PPL, METHOD == 2>(G, L, x, w, wx, y);
-    return 1.0 - chi2 / chi0;
+    return 1.0 - chi2 * G.inv_chi0;
 }
 
 // One work item: an object and a run of consecutive trial frequencies (a tile
@@ -1067,6 +1067,8 @@ __device__ void run_item(Group<P, NW, PPL> &G, unsigned char *lds, const Layout 
     od.y = (P::kIsF64 ? (const R *)L.cat.yc : (const R *)L.cat.yc32) + base;
     od.w = (P::kIsF64 ? (const R *)L.cat.w : (const R *)L.cat.w32) + base;
     const double chi0 = L.cat.chi0[obj];
+    G.inv_n = 1.0 / (double)G.n;  // once per item: the trials multiply
+    G.inv_chi0 = 1.0 / chi0;
     if constexpr (caches_object(kWave * NW * PPL)) {
         double *ct = (double *)(lds + Y.obj);
         R *cy = (R *)(lds + Y.obj + Y.np * 8);
@@ -1147,6 +1149,8 @@ void trial_kernel(TrialLaunch L) {
     G.ext = Y.ext;
     G.ties = false;
     G.vsmlsq = 0.0;
+    G.inv_n = 0.0;
+    G.inv_chi0 = 0.0;
     G.n = 0;
     const unsigned long long total = (unsigned long long)(*L.count) * (unsigned long long)L.n_tiles;
     unsigned long long *take = (unsigned long long *)(lds + Y.qslot);
