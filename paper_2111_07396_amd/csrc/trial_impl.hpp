@@ -899,8 +899,11 @@ __device__ double run_trial(Group<P, NW, PPL> &G, unsigned char *lds, const Layo
 #pragma unroll
     for (int p = 0; p < PPL; ++p) {
         const int j = t * PPL + p;
-        const double u = (kCache ? ct : od.tt)[min(j, n - 1)] * f;
-        const double ph = u - floor(u);
+        const double x = (kCache ? ct : od.tt)[min(j, n - 1)];
+        // fraction of the exact product tt f (one rounding, the same for every
+        // point); clamped at 0 where tt f lies just below an integer that its
+        // rounded value reached, so that ph is always in [0, 1)
+        const double ph = fmax(fma(x, f, -floor(x * f)), 0.0);
         const uint64_t ph48 = (uint64_t)(ph * 0x1p48);
         key[p] = j < n ? ((ph48 << 16) | (uint64_t)j) : ~0ull;
     }
