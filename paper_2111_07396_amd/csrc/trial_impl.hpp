@@ -904,7 +904,10 @@ __device__ double run_trial(Group<P, NW, PPL> &G, unsigned char *lds, const Layo
         // point); clamped at 0 where tt f lies just below an integer that its
         // rounded value reached, so that ph is always in [0, 1)
         const double ph = fmax(fma(x, f, -floor(x * f)), 0.0);
-        const uint64_t ph48 = (uint64_t)(ph * 0x1p48);
+        // floor(ph 2^48), an integer below 2^48: adding 2^52 places it exactly
+        // in the low mantissa bits (cheaper than a general double -> uint64)
+        const double q = floor(ph * 0x1p48) + 0x1p52;
+        const uint64_t ph48 = __builtin_bit_cast(uint64_t, q) & ((1ull << 52) - 1);
         key[p] = j < n ? ((ph48 << 16) | (uint64_t)j) : ~0ull;
     }
     // ---- bucket sort in LDS: NP buckets on the top phase bits, counts by LDS
