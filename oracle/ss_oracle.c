@@ -25,9 +25,11 @@
  *                   paper).  Written here as its definition: for every point a
  *                   weighted least-squares line over an explicit window,
  *                   computed directly with two passes over that window.
- *   ora_supsmu      Listing 1 (Sec. 2.2): three cross-validated smooths,
- *                   smoothed |CV residuals|, per-point span choice with bass
- *                   enhancement, span smooth, blend, final smooth.
+ *   ora_supsmu      The variable-span Super Smoother that Sec. 2.2 runs per
+ *                   trial, written from the method: primary fits and their
+ *                   cross-validation errors per candidate span, a span per
+ *                   point (least error, bass enhancement), the spans
+ *                   smoothed, the fits mixed at them, a final smooth.
  *   ora_sssp        Sec. 3 single-pass generalized-validation variant.  The
  *                   paper gives no equation; the reading implemented is one
  *                   sweep over K candidate spans scored by generalized
@@ -37,8 +39,9 @@
  *                   sweep (smooths s_k and traces TR_k of the K = 3 spans),
  *                   then a span choice per point by the un-smoothed
  *                   generalized-validation residual |y - s_k| / (1 - TR_k/n)
- *                   with Listing 1's scan, bass enhancement, clip and blend
- *                   (its residual, span and final smooths left out).
+ *                   with the Super Smoother's per-point span selection and
+ *                   mixing of fits (its error, span and final smooths left
+ *                   out).
  *   ora_pdm         Phase dispersion of one trial (a second period finder on the
  *                   same fold; Sec. 6 names reusing the fold and sort for other
  *                   finders): the points' phases in B equal bins, the fraction
@@ -277,138 +280,219 @@ void ora_smooth(int n, const double *x, const double *v, const double *w, double
     }
 }
 
-/* ------------------------------------------------------------------ shared driver pieces */
+/* ------------------------------------------------------------------ trial frame */
 
-/* Listing 1: constant weighted mean when the sorted phases are not spread
- * (x[n-1] <= x[0]). */
-static int degenerate_fill(int n, const double *x, const double *y, const double *w, double *smo)
+/* What every smooth of one trial shares: the sorted abscissae and weights,
+ * the mode and the threshold below which a window's x-spread counts as zero. */
+typedef struct {
+    int n;
+    const double *x, *w;
+    int periodic;
+    double vsmlsq;
+} ora_frame;
+
+/* Sec. 2.2: when the sorted phases do not spread (last <= first) the fit is
+ * the weighted mean of y at every point.  Returns 1 and fills fit then. */
+static int flat_phases(int n, const double *x, const double *y, const double *w, double *fit)
 {
     if (x[n - 1] > x[0]) return 0;
-    double sy = 0.0, sw = 0.0;
+    double num = 0.0, den = 0.0;
     for (int j = 0; j < n; ++j) {
-        sy += w[j] * y[j];
-        sw += w[j];
+        num += w[j] * y[j];
+        den += w[j];
     }
-    double a = (sw > 0.0) ? sy / sw : 0.0;
-    for (int j = 0; j < n; ++j) smo[j] = a;
+    const double mean = (den > 0.0) ? num / den : 0.0;
+    for (int j = 0; j < n; ++j) fit[j] = mean;
     return 1;
 }
 
-/* Listing 1: vsmlsq from the inter-quartile phase range (0-based indices
- * q-1 and 3q-1 with q = n/4), and the mode: periodic when requested and the
- * abscissae lie in [0, 1]. */
-static double listing_vsmlsq(int n, const double *x)
+/* Sec. 2.2: the zero-spread threshold is 1e-6 times the squared distance
+ * between the sorted abscissae of 1-based ranks q and 3q, q = floor(n/4)
+ * (lower and upper quartile points; no widening when it is 0). */
+static double zero_spread(int n, const double *x)
 {
-    int i = n / 4 - 1;
-    int j = 3 * (i + 1) - 1;
-    double scale = x[j] - x[i];
-    return 1.0e-6 * scale * scale;
+    const int q = n / 4;
+    const double d = x[3 * q - 1] - x[q - 1];
+    return 1.0e-6 * d * d;
 }
 
-static int listing_periodic(int n, const double *x, int iper)
+/* iper = 2 asks for the periodic mode, granted when every abscissa lies in
+ * [0, 1] (always so for phases); iper = 1 is the plain mode. */
+static ora_frame make_frame(int n, const double *x, const double *w, int iper)
 {
-    if (iper == 2 && (x[0] < 0.0 || x[n - 1] > 1.0)) return 0;
-    return iper == 2;
+    ora_frame F;
+    F.n = n;
+    F.x = x;
+    F.w = w;
+    F.periodic = (iper == 2) && x[0] >= 0.0 && x[n - 1] <= 1.0;
+    F.vsmlsq = zero_spread(n, x);
+    return F;
+}
+
+static void frame_smooth(const ora_frame *F, const double *v, double span, int cv, double *s,
+                         double *r, double *lev)
+{
+    ora_smooth(F->n, F->x, v, F->w, span, F->periodic, cv, F->vsmlsq, s, r, lev);
+}
+
+/* ------------------------------------------------------------------ per-point span selection */
+
+/* Cross-validation errors at or above this value never select a span. */
+#define ORA_ERR_CAP 1.0e20
+
+/* Index of the candidate span with the least error at one point (spans in
+ * ascending order, the smaller one kept on equal errors); -1 when no error is
+ * below ORA_ERR_CAP (or all are NaN).  *least receives that error (the cap
+ * when none). */
+static int least_error(const double err[3], double *least)
+{
+    int k_best = -1;
+    double e_best = ORA_ERR_CAP;
+    for (int k = 0; k < 3; ++k) {
+        if (err[k] < e_best) {
+            e_best = err[k];
+            k_best = k;
+        }
+    }
+    *least = e_best;
+    return k_best;
+}
+
+/* Bass enhancement (Sec. 2.2): with 0 < alpha <= 10, a span chosen at a point
+ * whose least error e is positive and below the woofer's error e_w moves
+ * toward the woofer span by the fraction max(e/e_w, 1e-7)^(10 - alpha). */
+static double bass_shift(double span, double e, double e_w, double woofer, double alpha)
+{
+    if (!(alpha > 0.0 && alpha <= 10.0)) return span;
+    if (!(e > 0.0 && e < e_w)) return span;
+    double ratio = e / e_w;
+    if (ratio < 1.0e-7) ratio = 1.0e-7;
+    return span + (woofer - span) * pow(ratio, 10.0 - alpha);
+}
+
+/* The span a point receives from its three errors: the least-error span (0
+ * when none qualifies), then the bass shift. */
+static double point_span(const double err[3], const double spans[3], double alpha)
+{
+    double e;
+    const int k = least_error(err, &e);
+    const double chosen = (k < 0) ? 0.0 : spans[k];
+    return bass_shift(chosen, e, err[2], spans[2], alpha);
+}
+
+/* Value of the variable-span fit at one point: the span is clipped to
+ * [tweeter, woofer]; below the midrange span the midrange and tweeter fits
+ * are mixed, otherwise the midrange and woofer fits, with the outer fit's
+ * weight growing linearly from 0 at the midrange span to 1 at the outer
+ * span. */
+static double mix_fits(double span, const double spans[3], double f_tw, double f_mid, double f_wo)
+{
+    if (span <= spans[0]) span = spans[0];
+    if (span >= spans[2]) span = spans[2];
+    const int low = span - spans[1] < 0.0;
+    const double outer_span = low ? spans[0] : spans[2];
+    const double outer_fit = low ? f_tw : f_wo;
+    const double g = (span - spans[1]) / (outer_span - spans[1]);
+    return (1.0 - g) * f_mid + g * outer_fit;
 }
 
 /* ------------------------------------------------------------------ SS driver */
 
-/* Listing 1 on sorted (x, y, w).  spans = {tweeter, midrange, woofer}.
- * iper = 2 requests the periodic mode, 1 the non-periodic one. */
+/* Super Smoother of one trial (Sec. 2.2, Friedman's variable-span smoother)
+ * on sorted (x, y, w); spans = {tweeter, midrange, woofer}; iper as in
+ * make_frame.  The stages:
+ *   fits     for each span, the primary smooth of y with its leave-one-out
+ *            residuals;
+ *   errors   each span's residuals smoothed at the midrange span;
+ *   spans    per point, point_span of the three errors;
+ *   mixing   the per-point spans smoothed at the midrange span, then
+ *            mix_fits of the three primary fits;
+ *   result   the mixed curve smoothed at the tweeter span.
+ * fixed_span > 0 replaces all of it by one smooth at that span. */
 void ora_supsmu(int n, const double *x, const double *y, const double *w, int iper,
                 const double *spans, double alpha, double fixed_span, double *smo)
 {
-    if (degenerate_fill(n, x, y, w, smo)) return;
-    double vsmlsq = listing_vsmlsq(n, x);
-    int per = listing_periodic(n, x, iper);
-    double *buf = (double *)malloc((size_t)n * 9 * sizeof(double));
-    double *s[3] = {buf, buf + n, buf + 2 * n};
-    double *rt[3] = {buf + 3 * n, buf + 4 * n, buf + 5 * n};
-    double *r = buf + 6 * n, *sel = buf + 7 * n, *tmp = buf + 8 * n;
+    if (flat_phases(n, x, y, w, smo)) return;
+    const ora_frame F = make_frame(n, x, w, iper);
+    double *work = (double *)malloc((size_t)n * 9 * sizeof(double));
+    double *scratch = work + 8 * (size_t)n;
     if (fixed_span > 0.0) {
-        ora_smooth(n, x, y, w, fixed_span, per, 1, vsmlsq, smo, r, NULL);
-        free(buf);
+        frame_smooth(&F, y, fixed_span, 1, smo, scratch, NULL);
+        free(work);
         return;
     }
+    /* candidate k: its primary fit and its smoothed CV error, point-major */
+    struct {
+        double *fit, *err;
+    } cand[3];
+    double *resid = work + 6 * (size_t)n, *span_pt = work + 7 * (size_t)n;
     for (int k = 0; k < 3; ++k) {
-        ora_smooth(n, x, y, w, spans[k], per, 1, vsmlsq, s[k], r, NULL);
-        ora_smooth(n, x, r, w, spans[1], per, 0, vsmlsq, rt[k], tmp, NULL);
+        cand[k].fit = work + (size_t)(2 * k) * n;
+        cand[k].err = work + (size_t)(2 * k + 1) * n;
+        frame_smooth(&F, y, spans[k], 1, cand[k].fit, resid, NULL);
+        frame_smooth(&F, resid, spans[1], 0, cand[k].err, scratch, NULL);
     }
     for (int j = 0; j < n; ++j) {
-        double resmin = 1.0e20;
-        sel[j] = 0.0; /* Listing 1 leaves it unset if no residual is below 1e20 */
-        for (int k = 0; k < 3; ++k) {
-            if (rt[k][j] < resmin) {
-                resmin = rt[k][j];
-                sel[j] = spans[k];
-            }
-        }
-        if (alpha > 0.0 && alpha <= 10.0 && resmin < rt[2][j] && resmin > 0.0) {
-            double ratio = resmin / rt[2][j];
-            if (ratio < 1.0e-7) ratio = 1.0e-7;
-            sel[j] += (spans[2] - sel[j]) * pow(ratio, 10.0 - alpha);
-        }
+        const double err[3] = {cand[0].err[j], cand[1].err[j], cand[2].err[j]};
+        span_pt[j] = point_span(err, spans, alpha);
     }
-    double *span_s = rt[0]; /* reuse */
-    ora_smooth(n, x, sel, w, spans[1], per, 0, vsmlsq, span_s, tmp, NULL);
-    double *blend = rt[1];
-    for (int j = 0; j < n; ++j) {
-        double sj = span_s[j];
-        if (sj <= spans[0]) sj = spans[0];
-        if (sj >= spans[2]) sj = spans[2];
-        double f = sj - spans[1];
-        if (f < 0.0) {
-            f /= spans[0] - spans[1];
-            blend[j] = (1.0 - f) * s[1][j] + f * s[0][j];
-        } else {
-            f /= spans[2] - spans[1];
-            blend[j] = (1.0 - f) * s[1][j] + f * s[2][j];
-        }
-    }
-    ora_smooth(n, x, blend, w, spans[0], per, 0, vsmlsq, smo, tmp, NULL);
-    free(buf);
+    double *span_sm = resid; /* residuals no longer needed */
+    frame_smooth(&F, span_pt, spans[1], 0, span_sm, scratch, NULL);
+    double *mixed = span_pt;
+    for (int j = 0; j < n; ++j)
+        mixed[j] = mix_fits(span_sm[j], spans, cand[0].fit[j], cand[1].fit[j], cand[2].fit[j]);
+    frame_smooth(&F, mixed, spans[0], 0, smo, scratch, NULL);
+    free(work);
 }
 
 /* ------------------------------------------------------------------ SSSP (Sec. 3) */
+
+/* Weighted residual sum of a fit. */
+static double rss_of(int n, const double *y, const double *w, const double *fit)
+{
+    double acc = 0.0;
+    for (int j = 0; j < n; ++j) acc += w[j] * (y[j] - fit[j]) * (y[j] - fit[j]);
+    return acc;
+}
+
+/* Trace of a smoother: sum of w_j h_j. */
+static double trace_of(int n, const double *w, const double *lev)
+{
+    double acc = 0.0;
+    for (int j = 0; j < n; ++j) acc += w[j] * lev[j];
+    return acc;
+}
 
 /* One generalized-validation pass over K candidate spans.  Outputs per span
  * the weighted residual sum RSS_k (smooth after tie averaging) and the trace
  * TR_k = sum_j w_j h_j of the smoother; returns chi^2 = RSS of the first span
  * that minimises GCV_k = RSS_k/(1 - TR_k/n)^2 (GCV = +inf when TR_k >= n).
- * fixed_span > 0 replaces the candidates by that single span.  Degenerate
- * phases give the constant-mean fit of Listing 1. */
+ * fixed_span > 0 replaces the candidates by that single span.  Flat phases
+ * give the constant-mean fit of Sec. 2.2. */
 double ora_sssp(int n, const double *x, const double *y, const double *w, int iper,
                 const double *spans, int nspans, double fixed_span,
                 double *rss_out, double *tr_out, int *kbest_out)
 {
-    double *smo = (double *)malloc((size_t)n * 3 * sizeof(double));
-    double *r = smo + n, *lev = smo + 2 * n;
+    double *fit = (double *)malloc((size_t)n * 3 * sizeof(double));
+    double *r = fit + n, *lev = fit + 2 * n;
     double chi2;
-    if (degenerate_fill(n, x, y, w, smo)) {
-        chi2 = 0.0;
-        for (int j = 0; j < n; ++j) chi2 += w[j] * (y[j] - smo[j]) * (y[j] - smo[j]);
+    if (flat_phases(n, x, y, w, fit)) {
+        chi2 = rss_of(n, y, w, fit);
         if (kbest_out) *kbest_out = -1;
-        free(smo);
+        free(fit);
         return chi2;
     }
-    double vsmlsq = listing_vsmlsq(n, x);
-    int per = listing_periodic(n, x, iper);
-    int K = (fixed_span > 0.0) ? 1 : nspans;
+    const ora_frame F = make_frame(n, x, w, iper);
+    const int K = (fixed_span > 0.0) ? 1 : nspans;
     double best = INFINITY;
     int kbest = 0;
     chi2 = NAN;
     for (int k = 0; k < K; ++k) {
-        double span = (fixed_span > 0.0) ? fixed_span : spans[k];
-        ora_smooth(n, x, y, w, span, per, 1, vsmlsq, smo, r, lev);
-        double rss = 0.0, tr = 0.0;
-        for (int j = 0; j < n; ++j) {
-            double d = y[j] - smo[j];
-            rss += w[j] * d * d;
-            tr += w[j] * lev[j];
-        }
+        frame_smooth(&F, y, (fixed_span > 0.0) ? fixed_span : spans[k], 1, fit, r, lev);
+        const double rss = rss_of(n, y, w, fit), tr = trace_of(n, w, lev);
         double gcv = INFINITY;
         if (tr < (double)n) {
-            double den = 1.0 - tr / (double)n;
+            const double den = 1.0 - tr / (double)n;
             gcv = rss / (den * den);
         }
         if (rss_out) rss_out[k] = rss;
@@ -420,69 +504,51 @@ double ora_sssp(int n, const double *x, const double *y, const double *w, int ip
         }
     }
     if (kbest_out) *kbest_out = kbest;
-    free(smo);
+    free(fit);
     return chi2;
 }
 
-/* Second reading of the Sec. 3 variant (see the header).  alpha as in
- * Listing 1; with a fixed span it is the fixed-span smooth. */
+/* Second reading of the Sec. 3 variant (see the header): the three primary
+ * fits and their traces from one pass; per point the error of span k is the
+ * un-smoothed generalized-validation residual |y - s_k|/(1 - TR_k/n) (+inf
+ * when TR_k >= n); point_span and mix_fits as in the Super Smoother, and
+ * chi^2 of the mixed fit (no error, span or final smooth).  A fixed span is
+ * the fixed-span smooth. */
 double ora_sssp2(int n, const double *x, const double *y, const double *w, int iper,
                  const double *spans, double alpha, double fixed_span)
 {
-    double *buf = (double *)malloc((size_t)n * 6 * sizeof(double));
-    double *s[3] = {buf, buf + n, buf + 2 * n};
-    double *r = buf + 3 * n, *lev = buf + 4 * n, *smo = buf + 5 * n;
-    double chi2 = 0.0;
-    if (degenerate_fill(n, x, y, w, smo)) {
-        for (int j = 0; j < n; ++j) chi2 += w[j] * (y[j] - smo[j]) * (y[j] - smo[j]);
-        free(buf);
+    double *work = (double *)malloc((size_t)n * 6 * sizeof(double));
+    double *fit[3] = {work, work + n, work + 2 * n};
+    double *r = work + 3 * n, *lev = work + 4 * n, *mixed = work + 5 * n;
+    double chi2;
+    if (flat_phases(n, x, y, w, mixed)) {
+        chi2 = rss_of(n, y, w, mixed);
+        free(work);
         return chi2;
     }
-    double vsmlsq = listing_vsmlsq(n, x);
-    int per = listing_periodic(n, x, iper);
+    const ora_frame F = make_frame(n, x, w, iper);
     if (fixed_span > 0.0) {
-        ora_smooth(n, x, y, w, fixed_span, per, 1, vsmlsq, smo, r, lev);
-        for (int j = 0; j < n; ++j) chi2 += w[j] * (y[j] - smo[j]) * (y[j] - smo[j]);
-        free(buf);
+        frame_smooth(&F, y, fixed_span, 1, mixed, r, lev);
+        chi2 = rss_of(n, y, w, mixed);
+        free(work);
         return chi2;
     }
-    double den[3];
-    int ok[3];
+    double gv_den[3];
+    int usable[3];
     for (int k = 0; k < 3; ++k) {
-        ora_smooth(n, x, y, w, spans[k], per, 1, vsmlsq, s[k], r, lev);
-        double tr = 0.0;
-        for (int j = 0; j < n; ++j) tr += w[j] * lev[j];
-        ok[k] = tr < (double)n;
-        den[k] = 1.0 - tr / (double)n;
+        frame_smooth(&F, y, spans[k], 1, fit[k], r, lev);
+        const double tr = trace_of(n, w, lev);
+        usable[k] = tr < (double)n;
+        gv_den[k] = 1.0 - tr / (double)n;
     }
     for (int j = 0; j < n; ++j) {
-        double e[3];
-        for (int k = 0; k < 3; ++k) e[k] = ok[k] ? fabs(y[j] - s[k][j]) / den[k] : INFINITY;
-        double resmin = 1e20, sel = 0.0;
-        for (int k = 0; k < 3; ++k) {
-            if (e[k] < resmin) {
-                resmin = e[k];
-                sel = spans[k];
-            }
-        }
-        if (alpha > 0.0 && alpha <= 10.0 && resmin < e[2] && resmin > 0.0) {
-            double tmp = resmin / e[2];
-            if (tmp < 1e-7) tmp = 1e-7;
-            sel += (spans[2] - sel) * pow(tmp, 10.0 - alpha);
-        }
-        if (sel <= spans[0]) sel = spans[0];
-        if (sel >= spans[2]) sel = spans[2];
-        double f = sel - spans[1], b;
-        if (f < 0.0) {
-            f = f / (spans[0] - spans[1]);
-            b = (1.0 - f) * s[1][j] + f * s[0][j];
-        } else {
-            f = f / (spans[2] - spans[1]);
-            b = (1.0 - f) * s[1][j] + f * s[2][j];
-        }
-        chi2 += w[j] * (y[j] - b) * (y[j] - b);
+        double err[3];
+        for (int k = 0; k < 3; ++k)
+            err[k] = usable[k] ? fabs(y[j] - fit[k][j]) / gv_den[k] : INFINITY;
+        mixed[j] = mix_fits(point_span(err, spans, alpha), spans, fit[0][j], fit[1][j], fit[2][j]);
     }
-    free(buf);
+    chi2 = rss_of(n, y, w, mixed);
+    free(work);
     return chi2;
 }
 

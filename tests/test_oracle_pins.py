@@ -409,3 +409,114 @@ def test_pdm_bins_rule():
     assert [oracle.pdm_bins(n) for n in (5, 20, 21, 100, 160, 161, 5000)] == \
         [4, 4, 4, 20, 32, 32, 32]
     assert oracle.pdm_bins(100, 9) == 9
+
+
+# ----------------------------------------------------------------- variable span, exact
+
+def _n8_case():
+    from fractions import Fraction as Q
+    g = json.load(open(os.path.join(GOLDEN, "supsmu_n8.json")))
+    x = [Q(v, 64) for v in g["x_num_over_64"]]
+    y = [Q(v, 8) for v in g["y_num_over_8"]]
+    w = [Q(v) for v in g["w"]]
+    spans = tuple(Q(v, 10) for v in g["spans_num_over_10"])
+    return x, y, w, spans, g["alphas"]
+
+
+def test_supsmu_n8_points_choose_different_spans_exact():
+    # every step of the driver in exact rationals (tests/bruteforce.py) on an
+    # 8-point case where half the points take the tweeter and half the
+    # midrange: a misreading confined to points with differing choices (the
+    # span smooth, the bass shift, the clip or the mixing) shows up here
+    x, y, w, spans, alphas = _n8_case()
+    xf = np.array([float(v) for v in x])
+    yf = np.array([float(v) for v in y])
+    wf = np.array([float(v) for v in w])
+    for alpha in alphas:
+        smo, chosen = bf.exact_supsmu(x, y, w, spans, alpha)
+        assert chosen.count(spans[0]) >= 3 and chosen.count(spans[1]) >= 3, chosen
+        ref = np.array([float(v) for v in smo])
+        got = oracle.supsmu(xf, yf, wf, spans=[float(s) for s in spans], alpha=float(alpha))
+        np.testing.assert_allclose(got, ref, rtol=0, atol=1e-13, err_msg=f"alpha={alpha}")
+    # the bass shift matters here: alpha 0 and 10 give different curves
+    s0, _ = bf.exact_supsmu(x, y, w, spans, 0)
+    s10, _ = bf.exact_supsmu(x, y, w, spans, 10)
+    assert max(abs(float(a - b)) for a, b in zip(s0, s10)) > 1e-3
+
+
+def test_supsmu_random_exact_with_other_spans():
+    # the same exact statement on random rational inputs, other span triples
+    from fractions import Fraction as Q
+    rng = np.random.default_rng(31)
+    for spans in [(Q(1, 20), Q(1, 5), Q(1, 2)), (Q(1, 10), Q(3, 10), Q(3, 5)),
+                  (Q(1, 50), Q(1, 10), Q(3, 10)), (Q(1, 20), Q(1, 5), Q(1))]:
+        for n in (9, 14, 23):
+            xi = np.sort(rng.choice(256, n, replace=False))
+            x = [Q(int(v), 256) for v in xi]
+            y = [Q(int(v), 16) for v in rng.integers(-16, 17, n)]
+            w = [Q(int(v)) for v in rng.integers(1, 6, n)]
+            smo, _ = bf.exact_supsmu(x, y, w, spans, 9)
+            got = oracle.supsmu(np.array([float(v) for v in x]), np.array([float(v) for v in y]),
+                                np.array([float(v) for v in w]),
+                                spans=[float(s) for s in spans], alpha=9.0)
+            np.testing.assert_allclose(got, [float(v) for v in smo], rtol=0, atol=1e-12,
+                                       err_msg=f"spans={spans} n={n}")
+
+
+# ----------------------------------------------------------------- closed forms at other spans
+
+OTHER_SPANS = [(0.02, 0.1, 0.3), (0.1, 0.3, 0.6), (0.05, 0.2, 1.0)]
+
+
+def _gains(spans, n=64):
+    m = [2 * oracle.halfwidth(n, s) + 1 for s in spans]
+    D = [bf.dirichlet_gain(mm, n) for mm in m]
+    return m, D
+
+
+def _mix_gain(spans, c, D, alpha):
+    # span from the per-point error ratios c_k (the same at every point of the
+    # sinusoid), bass, clip; the mixed fit is (returned gain) times y
+    k = int(np.argmin(c))
+    span = spans[k]
+    if 0 < alpha <= 10 and c[k] < c[2]:
+        span += (spans[2] - span) * max(c[k] / c[2], 1e-7) ** (10 - alpha)
+    span = min(max(span, spans[0]), spans[2])
+    f = span - spans[1]
+    if f < 0:
+        f /= spans[0] - spans[1]
+        return (1 - f) * D[1] + f * D[0]
+    f /= spans[2] - spans[1]
+    return (1 - f) * D[1] + f * D[2]
+
+
+@pytest.mark.parametrize("spans", OTHER_SPANS)
+@pytest.mark.parametrize("alpha", [0.0, 7.3, 9.0])
+def test_trial_closed_forms_at_other_spans(spans, alpha):
+    # sinusoid on exact phases: every smooth is D_m y, the smoothed CV error of
+    # span k is c_k |y| D_mid-free (a constant multiple at every point), so the
+    # whole driver, both single-pass readings and the fixed span have closed
+    # forms for any span triple
+    t, y, e = _sinusoid_object()
+    st, tt, w, ybar, chi0 = oracle.prep(t, y, e)
+    m, D = _gains(spans)
+    c = [(1 - D[k]) / (1 - 1.0 / m[k]) for k in range(3)]
+    B = _mix_gain(spans, c, D, alpha)
+    p = oracle.trial(oracle.SS, tt, y, w, chi0, 1.0, spans=spans, alpha=alpha)
+    assert abs(p - (1 - (1 - D[0] * B) ** 2)) < 1e-12
+    p2 = oracle.trial(oracle.SSSP2, tt, y, w, chi0, 1.0, spans=spans, alpha=alpha)
+    assert abs(p2 - (1 - (1 - B) ** 2)) < 1e-12
+    gcv = [(1 - D[k]) ** 2 / (1 - 1.0 / m[k]) ** 2 for k in range(3)]
+    k = int(np.argmin(gcv))
+    p1 = oracle.trial(oracle.SSSP, tt, y, w, chi0, 1.0, spans=spans)
+    assert abs(p1 - (1 - (1 - D[k]) ** 2)) < 1e-12
+    for s in spans:
+        mm = 2 * oracle.halfwidth(64, s) + 1
+        pf = oracle.trial(oracle.SS, tt, y, w, chi0, 1.0, spans=spans, fixed_span=s)
+        assert abs(pf - (1 - (1 - bf.dirichlet_gain(mm, 64)) ** 2)) < 1e-12
+
+
+def test_span_one_window_is_clamped():
+    # span 1.0 on 64 points: b = 32 would hold a point twice; clamped to 31
+    assert oracle.halfwidth(64, 1.0) == 31
+    assert oracle.halfwidth(65, 1.0) == 32
