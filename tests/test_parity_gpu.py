@@ -246,7 +246,9 @@ def test_long_light_curves(ctx, method):
     _assert_pgram_close(pg, po, what="long light curves")
     pg32, _ = _gpu_pgram(ctx, method, offs, t, y, e, grid, ssg.Params(precision=ssg.SS_FP32C))
     rel = np.abs(pg32 - po) / np.maximum(1 - po, 1e-12)
-    assert np.mean(rel > 1e-4) <= 0.05 and rel.max() <= 1e-2, rel.max()
+    # the compensated-FP32 bar: 1e-4 at >= 99.9 % of trials, 1e-2 everywhere
+    print(f"FP32c long curves: max {rel.max():.2e}, over 1e-4 {np.mean(rel > 1e-4):.2e}")
+    assert np.mean(rel > 1e-4) <= 1e-3 and rel.max() <= 1e-2, (rel.max(), np.mean(rel > 1e-4))
 
 
 def test_tile_size_does_not_change_results(ctx):
@@ -318,5 +320,79 @@ def test_ties_and_uneven_weights_on_every_shape(ctx, method, precision):
                     assert np.array_equal(so, sg)
                     _assert_pgram_close(pg, po, tol=TOL if precision == ssg.SS_FP64 else 1e-2,
                                         what=f"{name} {nw}x{ppl} grid={grid}")
+    finally:
+        ctx.set_shape(0, 0, 0)
+
+
+OTHER_SPANS = [(0.02, 0.1, 0.3), (0.1, 0.3, 0.6), (0.05, 0.2, 1.0)]
+
+
+@pytest.mark.parametrize("spans", OTHER_SPANS)
+@pytest.mark.parametrize("method", [oracle.SS, oracle.SSSP, oracle.SSSP2])
+def test_other_spans(ctx, method, spans):
+    # span parameters other than the defaults change the half-widths, the
+    # periodic extension and the LDS layout; lengths across several shapes
+    lens = [23, 70, 150, 200, 333, 600]
+    cats = [synth.make_catalog(1500 + i, 1, n, 900.0, (0.3, 5.0), 0.05, shapes=(i % 3,))
+            for i, n in enumerate(lens)]
+    offs = np.concatenate([[0], np.cumsum([c.offsets[-1] for c in cats])]).astype(np.int64)
+    t = np.concatenate([c.t for c in cats])
+    y = np.concatenate([c.y for c in cats])
+    e = np.concatenate([c.e for c in cats]) * np.random.default_rng(4).uniform(0.5, 2.0, offs[-1])
+    grid = (0.1, 6.0, 97)
+    prm = ssg.Params(span_min=spans[0], span_mid=spans[1], span_max=spans[2])
+    po, so = oracle.periodogram(method, offs, t, y, e, *grid, spans=spans)
+    pg, sg = _gpu_pgram(ctx, method, offs, t, y, e, grid, prm)
+    assert np.array_equal(so, sg)
+    _assert_pgram_close(pg, po, what=f"spans={spans} method={method}")
+    _assert_best_equal(pg, po)
+
+
+@pytest.mark.parametrize("alpha", [2.5, 7.3])
+@pytest.mark.parametrize("method", [oracle.SS, oracle.SSSP2])
+def test_fractional_alpha(ctx, method, alpha):
+    # non-integer 10 - alpha: the bass power goes through exp2/log2
+    cat, _ = synth.catalog_uneven(seed=23, n_obj=16)
+    grid = (0.1, 10.0, 301)
+    po, _ = oracle.periodogram(method, cat.offsets, cat.t, cat.y, cat.e, *grid, alpha=alpha)
+    pg, _ = _gpu_pgram(ctx, method, cat.offsets, cat.t, cat.y, cat.e, grid,
+                       ssg.Params(alpha=alpha))
+    _assert_pgram_close(pg, po, what=f"alpha={alpha} method={method}")
+    _assert_best_equal(pg, po)
+
+
+@pytest.mark.parametrize("spans", OTHER_SPANS)
+def test_sinusoid_closed_form_other_spans_on_gpu(ctx, spans):
+    from tests.test_oracle_pins import _sinusoid_object, _gains, _mix_gain
+    t, y, e = _sinusoid_object()
+    offs = np.array([0, t.size], dtype=np.int64)
+    m, D = _gains(spans)
+    c = [(1 - D[k]) / (1 - 1.0 / m[k]) for k in range(3)]
+    prm = ssg.Params(span_min=spans[0], span_mid=spans[1], span_max=spans[2], alpha=9.0)
+    pg, _ = _gpu_pgram(ctx, oracle.SS, offs, t, y, e, (1.0, 2.0, 4), prm)
+    assert abs(pg[0, 0] - (1 - (1 - D[0] * _mix_gain(spans, c, D, 9.0)) ** 2)) < 1e-12
+    pg, _ = _gpu_pgram(ctx, oracle.SSSP2, offs, t, y, e, (1.0, 2.0, 4), prm)
+    assert abs(pg[0, 0] - (1 - (1 - _mix_gain(spans, c, D, 9.0)) ** 2)) < 1e-12
+
+
+@pytest.mark.parametrize("method", [oracle.SS, oracle.SSSP, oracle.SSSP2])
+def test_every_kernel_at_other_spans(ctx, method):
+    # every compiled FP64 kernel at a non-default span triple, on several
+    # objects that fill most of its group (several work items per group)
+    spans = (0.1, 0.3, 0.6)
+    prm = ssg.Params(span_min=spans[0], span_mid=spans[1], span_max=spans[2])
+    grid = (0.2, 4.0, 41)
+    try:
+        for i, (nw, ppl) in enumerate(ssg.shapes()):
+            n = min(700, max(5, int(0.85 * 64 * nw * ppl)))
+            cat = synth.make_catalog(2900 + i, 3, n, 800.0, (0.3, 5.0), 0.05)
+            ctx.set_shape(0, 0, 0)
+            ctx.set_shape(n, nw, ppl)
+            po, _ = oracle.periodogram(method, cat.offsets, cat.t, cat.y, cat.e, *grid,
+                                       spans=spans)
+            pg, st = _gpu_pgram(ctx, method, cat.offsets, cat.t, cat.y, cat.e, grid, prm)
+            if (st == ssg.OBJ_TOO_LONG).all():
+                continue
+            _assert_pgram_close(pg, po, what=f"kernel {nw}x{ppl} n={n} spans={spans}")
     finally:
         ctx.set_shape(0, 0, 0)
