@@ -168,6 +168,66 @@ int ss_best_period(ss_ctx *ctx, int32_t method, const ss_catalog *cat, const ss_
                    const ss_params *params, int64_t *best_idx, double *best_period,
                    double *best_power, int32_t *obj_status, void *stream);
 
+/* ---- shared time sampling
+ *
+ * Objects observed at the same times (a survey field imaged together) fold
+ * and sort alike at every trial frequency (Sec. 2.2: the fold and the sort
+ * depend only on the times).  A shared catalog holds n_obj light curves of
+ * n_points each at the times t[n_points] (device, FP64, need not be sorted);
+ * y and e are device FP64 arrays [n_obj][n_points], object-major.  The
+ * library folds and sorts once per trial frequency for a batch of objects
+ * and runs the smoother of each object on that order.  Results, statuses and
+ * errors are those of ss_method_periodogram / ss_best_period on the same
+ * objects written as an ordinary catalog (offsets o * n_points, t repeated),
+ * except that a non-finite time gives every object SS_OBJ_NONFINITE. */
+typedef struct {
+    int64_t n_obj;
+    int64_t n_points;
+    const double *t; /* [n_points] */
+    const double *y; /* [n_obj][n_points] */
+    const double *e; /* [n_obj][n_points] */
+} ss_shared_catalog;
+
+int ss_shared_periodogram(ss_ctx *ctx, int32_t method, const ss_shared_catalog *cat,
+                          const ss_grid *grid, const ss_params *params, void *pgram,
+                          int32_t *obj_status, void *stream);
+int ss_shared_best_period(ss_ctx *ctx, int32_t method, const ss_shared_catalog *cat,
+                          const ss_grid *grid, const ss_params *params, int64_t *best_idx,
+                          double *best_period, double *best_power, int32_t *obj_status,
+                          void *stream);
+
+/* ---- memory planning and batched periodograms
+ *
+ * Sec. 4.1, Eq. 1 splits a search into N_b = r (beta s)^-1 batches, r being
+ * the estimated device footprint, s the device memory and beta = 0.75 a
+ * safety factor.  The fused kernels here keep no N_f x N_t scratch; what
+ * grows with a catalog is the periodogram itself (n_obj x n_freq values,
+ * 200 GB for a million objects x 50,000 frequencies in FP32).
+ * ss_plan_batches applies Eq. 1 to that footprint, r = fixed + n_obj * per,
+ * with fixed = 32 bytes per point of prep workspace and per = the output row
+ * (if want_pgram) + the per-tile partials + per-object arrays, and splits the
+ * objects: *objs_per_batch = floor((beta s - fixed) / per) (at most n_obj),
+ * *n_batches = ceil(n_obj / *objs_per_batch).  s = mem_bytes, or the
+ * device's free memory when mem_bytes = 0.  SS_ERR_OOM if not one object
+ * fits.
+ *
+ * ss_periodogram_batched computes the periodogram of a catalog in object
+ * batches of chunk_objs into the caller's device buffer `chunk`
+ * (chunk_objs x n_freq values of the precision's type) and after each batch
+ * waits for `stream` and calls sink(user, obj_begin, obj_end, chunk,
+ * obj_status + obj_begin) on the calling thread; the sink must take what it
+ * needs before returning (the next batch overwrites chunk).  Rows and
+ * statuses are those of ss_method_periodogram on the whole catalog. */
+typedef void (*ss_pgram_sink)(void *user, int64_t obj_begin, int64_t obj_end, const void *chunk,
+                              const int32_t *obj_status);
+int ss_plan_batches(ss_ctx *ctx, int64_t n_obj, int64_t n_points, const ss_grid *grid,
+                    int32_t precision, int32_t want_pgram, double beta, int64_t mem_bytes,
+                    int64_t *objs_per_batch, int64_t *n_batches);
+int ss_periodogram_batched(ss_ctx *ctx, int32_t method, const ss_catalog *cat,
+                           const ss_grid *grid, const ss_params *params, void *chunk,
+                           int64_t chunk_objs, ss_pgram_sink sink, void *user,
+                           int32_t *obj_status, void *stream);
+
 /* Trial-group shapes (autotuning).  One trial runs on a workgroup of `nw`
  * wavefronts whose threads hold `ppl` consecutive phase-sorted points each,
  * so a shape holds light curves of up to 64*nw*ppl points.  ss_num_shapes /
@@ -184,8 +244,10 @@ int ss_ctx_set_shape(ss_ctx *ctx, int32_t n_max, int32_t nw, int32_t ppl);
 int ss_ctx_set_tile(ss_ctx *ctx, int32_t tile_f);
 
 /* Kernel timing, for benchmarks.  With timing enabled, every call records HIP
- * events on its stream around each launch of the fused trial kernel (all size
- * classes).  ss_ctx_trial_kernel_ms waits for the last call's events and
+ * events on its stream around each launch of the fused trial kernel; when a
+ * call has several size classes, their launches run concurrently on internal
+ * streams forked from and joined to the call's stream, and one pair of events
+ * spans fork to join.  ss_ctx_trial_kernel_ms waits for the last call's events and
  * returns the summed duration of its trial-kernel launches in milliseconds
  * and their count.  Returns SS_ERR_INVALID_ARG if timing was off. */
 int ss_ctx_set_timing(ss_ctx *ctx, int enable);
@@ -279,6 +341,80 @@ int ss_bin_scores(ss_ctx *ctx, const ss_catalog *cat, const ss_grid *grid, float
  * The first call on a new grid uploads the bin table synchronously. */
 int ss_learned_best_period(ss_ctx *ctx, int32_t method, const ss_catalog *cat,
                            const ss_grid *grid, const ss_params *params, const float *enc_params,
+                           float gamma, int32_t top_k, int32_t margin, int32_t full_below,
+                           int64_t *best_idx, double *best_period, double *best_power,
+                           int32_t *obj_status, void *stream);
+
+/* ---- model object: a proposal network bound to one search grid
+ *
+ * The learned half of search-and-refine (Sec. 6) as one object: the encoder's
+ * SS_ENC_PARAMS FP32 master parameters (layout above), its Adam moments
+ * m and v, the Adam step count and hyper-parameters (beta1 0.9, beta2 0.999,
+ * eps 1e-8), and the grid it was trained for (its bins and feature
+ * frequencies follow from the grid).  The model lives on the device of the
+ * context that created or loaded it; it is not thread-safe.
+ *
+ * File format (ss_model_save / ss_model_load), little-endian:
+ *   bytes 0..7    "SSGPUMDL"
+ *   uint32        format version (1)
+ *   uint32        J = length of the JSON metadata
+ *   uint64        n_params; int32 step; float32 beta1, beta2, eps;
+ *   float64       f_min, f_max; int64 n_freq; uint64 array offset A
+ *   J bytes       JSON metadata (format, versions, layer layout, grid, bin
+ *                 rule, the 32 feature frequencies, step, Adam settings)
+ *   at byte A     float32 params[n_params], m[n_params], v[n_params]
+ * Loading checks the magic, the format version, n_params, the grid and the
+ * file length; the JSON is for readers and is not parsed. */
+typedef struct ss_model ss_model;
+
+/* New model for `grid` with parameters copied from the HOST array
+ * init_params[SS_ENC_PARAMS]; Adam state zero, step 0.  Synchronous. */
+int ss_model_create(ss_ctx *ctx, const ss_grid *grid, const float *init_params,
+                    ss_model **out);
+void ss_model_destroy(ss_model *model);
+
+/* Any of grid, step, device_params may be NULL.  *device_params points at
+ * the model's current parameters (device, SS_ENC_PARAMS floats, owned by the
+ * model; valid until ss_model_destroy). */
+int ss_model_info(const ss_model *model, ss_grid *grid, int32_t *step,
+                  const float **device_params);
+
+/* Copies the model's current parameters to dst (device, SS_ENC_PARAMS
+ * floats), asynchronously on `stream`. */
+int ss_model_copy_params(const ss_model *model, float *dst, void *stream);
+
+/* Writes the model to `path` (format above).  Waits for the model's device
+ * first, so that queued training steps are included.  Errors: SS_ERR_HIP,
+ * SS_ERR_INVALID_ARG when the file cannot be written. */
+int ss_model_save(const ss_model *model, const char *path);
+
+/* Reads a model written by ss_model_save onto ctx's device (synchronous).
+ * SS_ERR_INVALID_ARG for a missing, truncated or malformed file,
+ * SS_ERR_UNSUPPORTED for another format version. */
+int ss_model_load(ss_ctx *ctx, const char *path, ss_model **out);
+
+/* The file format on the host alone (no device): write / read the grid,
+ * the step count and HOST arrays params, adam_m, adam_v of SS_ENC_PARAMS
+ * floats each.  Errors as for ss_model_save / ss_model_load; a file whose
+ * Adam settings differ from the fixed ones above is rejected. */
+int ss_model_file_write(const char *path, const ss_grid *grid, int32_t step,
+                        const float *params, const float *adam_m, const float *adam_v);
+int ss_model_file_read(const char *path, ss_grid *grid, int32_t *step, float *params,
+                       float *adam_m, float *adam_v);
+
+/* One training step: the mean cross-entropy gradient of the batch
+ * (as ss_enc_train_grad on the model's grid; labels[n_obj] device int32,
+ * *loss device float) followed by one Adam step with learning rate lr on the
+ * model's parameters and moments; the model's step count goes up by one.
+ * Asynchronous on `stream`. */
+int ss_train_step(ss_ctx *ctx, ss_model *model, const ss_catalog *batch, const int32_t *labels,
+                  float lr, float *loss, int32_t *obj_status, void *stream);
+
+/* Search-and-refine with a model: ss_learned_best_period with the model's
+ * parameters.  `grid` must be the grid the model was made for
+ * (SS_ERR_INVALID_ARG otherwise). */
+int ss_best_period_learned(ss_ctx *ctx, const ss_model *model, int32_t method,
+                           const ss_catalog *cat, const ss_grid *grid, const ss_params *params,
                            float gamma, int32_t top_k, int32_t margin, int32_t full_below,
                            int64_t *best_idx, double *best_period, double *best_power,
                            int32_t *obj_status, void *stream);

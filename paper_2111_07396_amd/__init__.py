@@ -31,7 +31,11 @@ EXPORTED = ("ss_params_default", "ss_ctx_create", "ss_ctx_destroy", "ss_periodog
             "ss_last_error", "ss_version", "ss_bin_table", "ss_enc_num_params", "ss_enc_forward",
             "ss_enc_train_grad", "ss_adam_step", "ss_refine_best_period",
             "ss_learned_best_period", "ss_bin_scores", "ss_method_periodogram",
-            "ss_pdm_periodogram")
+            "ss_pdm_periodogram", "ss_model_create", "ss_model_destroy", "ss_model_info",
+            "ss_model_save", "ss_model_load", "ss_model_file_write", "ss_model_file_read",
+            "ss_train_step", "ss_best_period_learned", "ss_model_copy_params",
+            "ss_shared_periodogram", "ss_shared_best_period", "ss_plan_batches",
+            "ss_periodogram_batched")
 ENC_PARAMS = 145536
 ENC_BINS = 1024
 
@@ -65,6 +69,11 @@ class _Params(ctypes.Structure):
                 ("flags", ctypes.c_int32)]
 
 
+class _SharedCatalog(ctypes.Structure):
+    _fields_ = [("n_obj", ctypes.c_int64), ("n_points", ctypes.c_int64),
+                ("t", ctypes.c_void_p), ("y", ctypes.c_void_p), ("e", ctypes.c_void_p)]
+
+
 class _Catalog(ctypes.Structure):
     _fields_ = [("n_obj", ctypes.c_int64), ("n_points", ctypes.c_int64),
                 ("offsets", ctypes.c_void_p),
@@ -72,6 +81,8 @@ class _Catalog(ctypes.Structure):
 
 
 _lib = None
+_SINK = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p,
+                         ctypes.c_void_p)
 
 
 def load_library(path: str = LIB_PATH):
@@ -145,6 +156,48 @@ def load_library(path: str = LIB_PATH):
     lib.ss_bin_scores.argtypes = [vp, ctypes.POINTER(_Catalog), ctypes.POINTER(_Grid), vp, vp,
                                   vp]
     lib.ss_bin_scores.restype = ctypes.c_int
+    lib.ss_shared_periodogram.argtypes = [vp, i32, ctypes.POINTER(_SharedCatalog),
+                                          ctypes.POINTER(_Grid), ctypes.POINTER(_Params), vp, vp,
+                                          vp]
+    lib.ss_shared_periodogram.restype = ctypes.c_int
+    lib.ss_shared_best_period.argtypes = [vp, i32, ctypes.POINTER(_SharedCatalog),
+                                          ctypes.POINTER(_Grid), ctypes.POINTER(_Params), vp, vp,
+                                          vp, vp, vp]
+    lib.ss_shared_best_period.restype = ctypes.c_int
+    lib.ss_plan_batches.argtypes = [vp, i64, i64, ctypes.POINTER(_Grid), i32, i32,
+                                    ctypes.c_double, i64, ctypes.POINTER(i64),
+                                    ctypes.POINTER(i64)]
+    lib.ss_plan_batches.restype = ctypes.c_int
+    lib.ss_periodogram_batched.argtypes = [vp, i32, ctypes.POINTER(_Catalog),
+                                           ctypes.POINTER(_Grid), ctypes.POINTER(_Params), vp,
+                                           i64, _SINK, vp, vp, vp]
+    lib.ss_periodogram_batched.restype = ctypes.c_int
+    fp = ctypes.POINTER(ctypes.c_float)
+    lib.ss_model_create.argtypes = [vp, ctypes.POINTER(_Grid), fp, ctypes.POINTER(vp)]
+    lib.ss_model_create.restype = ctypes.c_int
+    lib.ss_model_destroy.argtypes = [vp]
+    lib.ss_model_destroy.restype = None
+    lib.ss_model_info.argtypes = [vp, ctypes.POINTER(_Grid), ctypes.POINTER(i32),
+                                  ctypes.POINTER(vp)]
+    lib.ss_model_info.restype = ctypes.c_int
+    lib.ss_model_save.argtypes = [vp, ctypes.c_char_p]
+    lib.ss_model_save.restype = ctypes.c_int
+    lib.ss_model_load.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(vp)]
+    lib.ss_model_load.restype = ctypes.c_int
+    lib.ss_model_file_write.argtypes = [ctypes.c_char_p, ctypes.POINTER(_Grid), i32, fp, fp, fp]
+    lib.ss_model_file_write.restype = ctypes.c_int
+    lib.ss_model_file_read.argtypes = [ctypes.c_char_p, ctypes.POINTER(_Grid),
+                                       ctypes.POINTER(i32), fp, fp, fp]
+    lib.ss_model_file_read.restype = ctypes.c_int
+    lib.ss_model_copy_params.argtypes = [vp, vp, vp]
+    lib.ss_model_copy_params.restype = ctypes.c_int
+    lib.ss_train_step.argtypes = [vp, vp, ctypes.POINTER(_Catalog), vp, ctypes.c_float, vp, vp,
+                                  vp]
+    lib.ss_train_step.restype = ctypes.c_int
+    lib.ss_best_period_learned.argtypes = [vp, vp, i32, ctypes.POINTER(_Catalog),
+                                           ctypes.POINTER(_Grid), ctypes.POINTER(_Params),
+                                           ctypes.c_float, i32, i32, i32, vp, vp, vp, vp, vp]
+    lib.ss_best_period_learned.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -198,6 +251,35 @@ class DeviceCatalog:
             raise ValueError("t, y and e must have the same length")
         return _Catalog(self.n_obj, self.t.numel(), self.offsets.data_ptr(), self.t.data_ptr(),
                         self.y.data_ptr(), self.e.data_ptr())
+
+
+@dataclass
+class SharedCatalog:
+    """Light curves observed at one set of times (device, float64): t [n],
+    y and e [n_obj, n]."""
+    t: torch.Tensor
+    y: torch.Tensor
+    e: torch.Tensor
+
+    @property
+    def n_obj(self) -> int:
+        return int(self.y.shape[0])
+
+    @staticmethod
+    def from_numpy(t, y, e, device="cuda") -> "SharedCatalog":
+        def tt(a):
+            return torch.as_tensor(a, dtype=torch.float64).to(device).contiguous()
+        return SharedCatalog(tt(t), tt(y), tt(e))
+
+    def _c(self) -> _SharedCatalog:
+        n = self.t.numel()
+        for a in (self.t, self.y, self.e):
+            if a.dtype != torch.float64 or not a.is_cuda or not a.is_contiguous():
+                raise ValueError("shared catalog tensors must be contiguous CUDA float64")
+        if self.y.dim() != 2 or self.y.shape != self.e.shape or self.y.shape[1] != n:
+            raise ValueError("y and e must be [n_obj, n] with n = len(t)")
+        return _SharedCatalog(self.n_obj, n, self.t.data_ptr(), self.y.data_ptr(),
+                              self.e.data_ptr())
 
 
 def bin_table(grid):
@@ -346,6 +428,82 @@ class Context:
                                    ctypes.c_void_p(st.data_ptr()), _stream_ptr(stream)))
         return bi, bp, bw, st
 
+    def plan_batches(self, n_obj, n_points, grid, precision=SS_FP64, want_pgram=True,
+                     beta=0.75, mem_bytes=0):
+        """(objects per batch, number of batches) from the memory model of
+        ss_plan_batches (Eq. 1 of Sec. 4.1 on the periodogram footprint)."""
+        g = _Grid(float(grid[0]), float(grid[1]), int(grid[2]))
+        per = ctypes.c_int64(0)
+        nb = ctypes.c_int64(0)
+        _check(_lib.ss_plan_batches(self._h, int(n_obj), int(n_points), ctypes.byref(g),
+                                    int(precision), int(bool(want_pgram)), float(beta),
+                                    int(mem_bytes), ctypes.byref(per), ctypes.byref(nb)))
+        return per.value, nb.value
+
+    def periodogram_batched(self, method, cat: DeviceCatalog, grid, params=None, beta=0.75,
+                            mem_bytes=0, sink=None, stream=None):
+        """Periodogram in object batches planned by plan_batches.  Each batch is
+        computed into one reused device chunk; `sink(lo, hi, chunk_rows, status)`
+        receives it (default: gather into host arrays, returned as
+        (pgram [n_obj, n_freq] numpy, status numpy, n_batches))."""
+        import numpy as np
+        params = params or Params()
+        n_obj = cat.n_obj
+        per, nb = self.plan_batches(n_obj, cat.t.numel(), grid, params.precision, True, beta,
+                                    mem_bytes)
+        dt = torch.float64 if params.precision == SS_FP64 else torch.float32
+        dev = cat.offsets.device
+        chunk = torch.empty((max(per, 1), int(grid[2])), dtype=dt, device=dev)
+        status = torch.empty(n_obj, dtype=torch.int32, device=dev)
+        host = None
+        if sink is None:
+            host = np.empty((n_obj, int(grid[2])), dtype=np.float64 if dt == torch.float64
+                            else np.float32)
+
+            def sink(lo, hi, rows, st):
+                host[lo:hi] = rows.cpu().numpy()
+
+        def _cb(user, lo, hi, ptr, st_ptr):
+            sink(lo, hi, chunk[:hi - lo], status[lo:hi])
+
+        cb = _SINK(_cb)
+        g = _Grid(float(grid[0]), float(grid[1]), int(grid[2]))
+        c = cat._c()
+        p = params._c()
+        _check(_lib.ss_periodogram_batched(self._h, int(method), ctypes.byref(c),
+                                           ctypes.byref(g), ctypes.byref(p), _ptr(chunk),
+                                           int(per), cb, None, _ptr(status),
+                                           _stream_ptr(stream)))
+        return host, status.cpu().numpy(), nb
+
+    def shared_periodogram(self, method, cat: SharedCatalog, grid, params=None, stream=None):
+        """(P [n_obj, n_freq], status) of objects that share their times."""
+        params = params or Params()
+        dt = torch.float64 if params.precision == SS_FP64 else torch.float32
+        dev = cat.t.device
+        pg = torch.empty((cat.n_obj, int(grid[2])), dtype=dt, device=dev)
+        st = torch.empty(cat.n_obj, dtype=torch.int32, device=dev)
+        g = _Grid(float(grid[0]), float(grid[1]), int(grid[2]))
+        c = cat._c()
+        p = params._c()
+        _check(_lib.ss_shared_periodogram(self._h, int(method), ctypes.byref(c), ctypes.byref(g),
+                                          ctypes.byref(p), _ptr(pg), _ptr(st),
+                                          _stream_ptr(stream)))
+        return pg, st
+
+    def shared_best_period(self, method, cat: SharedCatalog, grid, params=None, out=None,
+                           stream=None):
+        """(best_idx, best_period, best_power, status) of objects that share their times."""
+        params = params or Params()
+        bi, bp, bw, st = self._best_out(cat.n_obj, cat.t.device, out)
+        g = _Grid(float(grid[0]), float(grid[1]), int(grid[2]))
+        c = cat._c()
+        p = params._c()
+        _check(_lib.ss_shared_best_period(self._h, int(method), ctypes.byref(c), ctypes.byref(g),
+                                          ctypes.byref(p), _ptr(bi), _ptr(bp), _ptr(bw), _ptr(st),
+                                          _stream_ptr(stream)))
+        return bi, bp, bw, st
+
     def _best_out(self, n_obj, dev, out):
         if out is None:
             out = (torch.empty(n_obj, dtype=torch.int64, device=dev),
@@ -430,6 +588,117 @@ class Context:
         ep = _ptr(enc_params) if enc_params is not None else ctypes.c_void_p(None)
         _check(_lib.ss_learned_best_period(self._h, int(method), ctypes.byref(c),
                                            ctypes.byref(g), ctypes.byref(p), ep, float(gamma),
+                                           int(top_k), int(margin), int(full_below), _ptr(bi),
+                                           _ptr(bp), _ptr(bw), _ptr(st), _stream_ptr(stream)))
+        return bi, bp, bw, st
+
+
+def _f32_host(a, what):
+    import numpy as np
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    if a.size != ENC_PARAMS:
+        raise ValueError(f"{what} must hold {ENC_PARAMS} floats")
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+def model_file_write(path, grid, step, params, adam_m, adam_v):
+    """Writes a model file from host arrays (no device needed)."""
+    lib = load_library()
+    g = _Grid(float(grid[0]), float(grid[1]), int(grid[2]))
+    keep = [_f32_host(a, w) for a, w in ((params, "params"), (adam_m, "adam_m"),
+                                         (adam_v, "adam_v"))]
+    _check(lib.ss_model_file_write(os.fsencode(path), ctypes.byref(g), int(step),
+                                   *[k[1] for k in keep]))
+
+
+def model_file_read(path):
+    """(grid, step, params, adam_m, adam_v) from a model file, on the host."""
+    import numpy as np
+    lib = load_library()
+    g = _Grid()
+    st = ctypes.c_int32(0)
+    arrs = [np.empty(ENC_PARAMS, dtype=np.float32) for _ in range(3)]
+    ptrs = [a.ctypes.data_as(ctypes.POINTER(ctypes.c_float)) for a in arrs]
+    _check(lib.ss_model_file_read(os.fsencode(path), ctypes.byref(g), ctypes.byref(st), *ptrs))
+    return (g.f_min, g.f_max, g.n_freq), st.value, arrs[0], arrs[1], arrs[2]
+
+
+class Model:
+    """An ss_model: encoder parameters, Adam state and the grid they belong to."""
+
+    def __init__(self, handle):
+        self._h = handle
+
+    @staticmethod
+    def create(ctx: "Context", grid, params) -> "Model":
+        lib = load_library()
+        g = _Grid(float(grid[0]), float(grid[1]), int(grid[2]))
+        a, ap = _f32_host(params, "params")
+        h = ctypes.c_void_p()
+        _check(lib.ss_model_create(ctx._h, ctypes.byref(g), ap, ctypes.byref(h)))
+        return Model(h)
+
+    @staticmethod
+    def load(ctx: "Context", path) -> "Model":
+        lib = load_library()
+        h = ctypes.c_void_p()
+        _check(lib.ss_model_load(ctx._h, os.fsencode(path), ctypes.byref(h)))
+        return Model(h)
+
+    def save(self, path):
+        _check(_lib.ss_model_save(self._h, os.fsencode(path)))
+
+    def info(self):
+        """(grid, step, device pointer of the parameters)."""
+        g = _Grid()
+        st = ctypes.c_int32(0)
+        p = ctypes.c_void_p()
+        _check(_lib.ss_model_info(self._h, ctypes.byref(g), ctypes.byref(st), ctypes.byref(p)))
+        return (g.f_min, g.f_max, g.n_freq), st.value, p.value
+
+    def params(self, device="cuda", stream=None) -> torch.Tensor:
+        """A copy of the current parameters as a float32 device tensor."""
+        out = torch.empty(ENC_PARAMS, dtype=torch.float32, device=device)
+        _check(_lib.ss_model_copy_params(self._h, _ptr(out), _stream_ptr(stream)))
+        return out
+
+    def close(self):
+        if self._h:
+            _lib.ss_model_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def train_step(self, ctx: "Context", batch: DeviceCatalog, labels: torch.Tensor, lr: float,
+                   loss: torch.Tensor | None = None, stream=None):
+        """Gradient of the batch plus one Adam step; returns the loss tensor [1]."""
+        n_obj = batch.n_obj
+        if labels.dtype != torch.int32 or not labels.is_cuda or labels.numel() != n_obj:
+            raise ValueError("labels must be a CUDA int32 tensor of n_obj elements")
+        labels = labels.contiguous()
+        dev = batch.offsets.device
+        if loss is None:
+            loss = torch.empty(1, dtype=torch.float32, device=dev)
+        st = torch.empty(n_obj, dtype=torch.int32, device=dev)
+        c = batch._c()
+        _check(_lib.ss_train_step(ctx._h, self._h, ctypes.byref(c), _ptr(labels),
+                                  float(lr), _ptr(loss), _ptr(st), _stream_ptr(stream)))
+        return loss
+
+    def best_period(self, ctx: "Context", method, cat: DeviceCatalog, grid, gamma=0.0, top_k=16,
+                    margin=1, full_below=0, params=None, out=None, stream=None):
+        """Search-and-refine with this model (ss_best_period_learned)."""
+        params = params or Params()
+        bi, bp, bw, st = ctx._best_out(cat.n_obj, cat.offsets.device, out)
+        g = _Grid(float(grid[0]), float(grid[1]), int(grid[2]))
+        c = cat._c()
+        p = params._c()
+        _check(_lib.ss_best_period_learned(ctx._h, self._h, int(method), ctypes.byref(c),
+                                           ctypes.byref(g), ctypes.byref(p), float(gamma),
                                            int(top_k), int(margin), int(full_below), _ptr(bi),
                                            _ptr(bp), _ptr(bw), _ptr(st), _stream_ptr(stream)))
         return bi, bp, bw, st

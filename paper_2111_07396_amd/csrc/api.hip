@@ -6,6 +6,8 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <fstream>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -88,10 +90,25 @@ struct DevBuf {
 
 }  // namespace
 
+// Device pointers of one call's workspace: the context's own buffers, or a
+// fixed region (the allocation-free entry point).
+struct Work {
+    double *tt = nullptr, *w = nullptr, *yc = nullptr;
+    float *w32 = nullptr, *yc32 = nullptr;
+    double *chi0 = nullptr, *sw = nullptr;
+    int32_t *objs = nullptr, *counts = nullptr;
+    unsigned long long *queues = nullptr;
+    double *part_p = nullptr;
+    int32_t *part_k = nullptr;
+};
+
 struct ss_ctx {
     int device = 0;
+    Work cur;                      // workspace of the call in progress
+    const Work *fixed = nullptr;   // when set: use it, never allocate
     DevBuf tt, w, yc, w32, yc32, chi0, sw, objs, counts, queues, part_p, part_k;
     DevBuf emb, act, logits, dlog, loss_o, dE, partial, ranges, bin_k, scores;
+    DevBuf sh_offsets, sh_tt;  // shared time sampling: CSR offsets o*n, t - min t
     double bin_grid[3] = {0.0, 0.0, 0.0};  // grid whose bin table is in bin_k
     int max_lds = 65536;
     int n_cu = 1;
@@ -100,6 +117,24 @@ struct ss_ctx {
     bool timing = false;
     hipEvent_t ev[2 * kNumShapes] = {};
     int n_timed = 0;
+    // class launches of one call run concurrently: forked from the caller's
+    // stream onto these (default-priority) streams and joined back to it
+    bool forked = false;
+    hipStream_t side[kNumShapes] = {};
+    hipEvent_t fork_ev = nullptr, join_ev[kNumShapes] = {};
+    int64_t chunk_bytes = 0;  // batched periodogram: the current output chunk
+    DevBuf chunk;
+};
+
+// A learned frequency proposal bound to one search grid: the encoder's FP32
+// master parameters, Adam moments and step count, all on the device of the
+// context that made it.
+struct ss_model {
+    int device = 0;
+    ss_grid grid{};
+    int32_t step = 0;
+    float beta1 = 0.9f, beta2 = 0.999f, eps = 1e-8f;
+    DevBuf params, m, v, grad;
 };
 
 #define SS_HIP_TRY(expr, what)                                                               \
@@ -145,6 +180,20 @@ int32_t choose_tile(int64_t n_obj, int64_t n_freq) {
     return (int32_t)std::min<int64_t>(t, n_freq);
 }
 
+int check_grid(const ss_grid *grid) {
+    if (!grid) return fail(SS_ERR_INVALID_ARG, "null grid");
+    if (!(grid->n_freq >= 1) || grid->n_freq > INT32_MAX)
+        return fail(SS_ERR_INVALID_ARG, "n_freq must be in [1, 2^31)");
+    if (!(std::isfinite(grid->f_min) && std::isfinite(grid->f_max) && grid->f_min > 0.0 &&
+          grid->f_max > grid->f_min))
+        return fail(SS_ERR_INVALID_ARG, "grid needs 0 < f_min < f_max");
+    return SS_OK;
+}
+
+// Objects per work item under shared time sampling (at most kMaxSharedBatch).
+constexpr int32_t kSharedBatch = 8;
+static_assert(kSharedBatch <= kMaxSharedBatch, "shared batch");
+
 // Everything a launch over a catalog needs after prep.
 struct Plan {
     ShapeRules R{};
@@ -155,7 +204,7 @@ struct Plan {
 // Reset plus prep (with device-side planning of the shape classes).  Nothing
 // here waits for the device.
 int prepare(ss_ctx *ctx, int method, const ss_catalog *cat, const ss_params *prm,
-            int32_t *obj_status, hipStream_t stream, Plan &P) {
+            int32_t *obj_status, hipStream_t stream, Plan &P, bool shared_t = false) {
     const int64_t n_obj = cat->n_obj;
     const int64_t total = cat->n_points;
     SS_HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
@@ -187,25 +236,50 @@ int prepare(ss_ctx *ctx, int method, const ss_catalog *cat, const ss_params *prm
     for (int i = 0; i < R.n_def; ++i) P.used[R.def_shape[i]] = true;
     P.used[R.fallback] = true;
 
-    SS_HIP_TRY(ctx->tt.ensure((size_t)total * 8), "workspace");
-    SS_HIP_TRY(ctx->w.ensure((size_t)total * 8), "workspace");
-    SS_HIP_TRY(ctx->yc.ensure((size_t)total * 8), "workspace");
-    SS_HIP_TRY(ctx->w32.ensure((size_t)total * 4), "workspace");
-    SS_HIP_TRY(ctx->yc32.ensure((size_t)total * 4), "workspace");
-    SS_HIP_TRY(ctx->chi0.ensure((size_t)n_obj * 8), "workspace");
-    SS_HIP_TRY(ctx->sw.ensure((size_t)n_obj * 8), "workspace");
-    SS_HIP_TRY(ctx->objs.ensure((size_t)n_obj * kNumShapes * 4), "workspace");
-    SS_HIP_TRY(ctx->counts.ensure((size_t)kNumShapes * 4), "workspace");
-    SS_HIP_TRY(ctx->queues.ensure((size_t)kNumShapes * 8), "workspace");
-    int32_t *counts = (int32_t *)ctx->counts.p;
-    unsigned long long *queues = (unsigned long long *)ctx->queues.p;
+    if (ctx->fixed) {
+        ctx->cur = *ctx->fixed;
+    } else {
+        SS_HIP_TRY(ctx->tt.ensure((size_t)total * 8), "workspace");
+        SS_HIP_TRY(ctx->w.ensure((size_t)total * 8), "workspace");
+        SS_HIP_TRY(ctx->yc.ensure((size_t)total * 8), "workspace");
+        SS_HIP_TRY(ctx->w32.ensure((size_t)total * 4), "workspace");
+        SS_HIP_TRY(ctx->yc32.ensure((size_t)total * 4), "workspace");
+        SS_HIP_TRY(ctx->chi0.ensure((size_t)n_obj * 8), "workspace");
+        SS_HIP_TRY(ctx->sw.ensure((size_t)n_obj * 8), "workspace");
+        SS_HIP_TRY(ctx->objs.ensure((size_t)n_obj * kNumShapes * 4), "workspace");
+        SS_HIP_TRY(ctx->counts.ensure((size_t)kNumShapes * 4), "workspace");
+        SS_HIP_TRY(ctx->queues.ensure((size_t)kNumShapes * 8), "workspace");
+        Work &W = ctx->cur;
+        W.tt = (double *)ctx->tt.p;
+        W.w = (double *)ctx->w.p;
+        W.yc = (double *)ctx->yc.p;
+        W.w32 = (float *)ctx->w32.p;
+        W.yc32 = (float *)ctx->yc32.p;
+        W.chi0 = (double *)ctx->chi0.p;
+        W.sw = (double *)ctx->sw.p;
+        W.objs = (int32_t *)ctx->objs.p;
+        W.counts = (int32_t *)ctx->counts.p;
+        W.queues = (unsigned long long *)ctx->queues.p;
+    }
+    int32_t *counts = ctx->cur.counts;
+    unsigned long long *queues = ctx->cur.queues;
     SS_HIP_TRY(launch_reset(counts, queues, kNumShapes, stream), "reset kernel");
     SS_HIP_TRY(launch_prep(cat->offsets, cat->t, cat->y, cat->e, n_obj, total,
-                           (double *)ctx->tt.p, (double *)ctx->w.p, (double *)ctx->yc.p,
-                           (float *)ctx->w32.p, (float *)ctx->yc32.p, (double *)ctx->chi0.p,
-                           (double *)ctx->sw.p, obj_status, R, (int32_t *)ctx->objs.p, counts,
-                           stream),
+                           ctx->cur.tt, ctx->cur.w, ctx->cur.yc, ctx->cur.w32, ctx->cur.yc32,
+                           ctx->cur.chi0, ctx->cur.sw, obj_status, R, ctx->cur.objs, counts,
+                           stream, shared_t),
                "prep kernel");
+    return SS_OK;
+}
+
+int ensure_side_streams(ss_ctx *ctx) {
+    if (ctx->forked) return SS_OK;
+    for (int i = 0; i < kNumShapes; ++i) {
+        SS_HIP_TRY(hipStreamCreateWithFlags(&ctx->side[i], hipStreamNonBlocking), "stream");
+        SS_HIP_TRY(hipEventCreateWithFlags(&ctx->join_ev[i], hipEventDisableTiming), "event");
+    }
+    SS_HIP_TRY(hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming), "event");
+    ctx->forked = true;
     return SS_OK;
 }
 
@@ -216,22 +290,25 @@ int trials(ss_ctx *ctx, const Plan &P, int method, const ss_catalog *cat, const 
            const ss_params *prm, double *pgram64, float *pgram32, bool want_best,
            int32_t *obj_status, hipStream_t stream, int64_t *best_idx, double *best_period,
            double *best_power, int32_t tile, int32_t n_tiles, const int64_t *ranges,
-           void *pdm = nullptr, int32_t pdm_bins = 0) {
+           void *pdm = nullptr, int32_t pdm_bins = 0, int shared_class = -1,
+           int32_t shared_batch = 0, int32_t shared_n = 0, const double *shared_tt = nullptr) {
     const int64_t n_obj = cat->n_obj;
-    if (want_best) {
+    if (want_best && !ctx->fixed) {
         SS_HIP_TRY(ctx->part_p.ensure((size_t)n_obj * n_tiles * 8), "workspace");
         SS_HIP_TRY(ctx->part_k.ensure((size_t)n_obj * n_tiles * 4), "workspace");
+        ctx->cur.part_p = (double *)ctx->part_p.p;
+        ctx->cur.part_k = (int32_t *)ctx->part_k.p;
     }
-    int32_t *counts = (int32_t *)ctx->counts.p;
-    unsigned long long *queues = (unsigned long long *)ctx->queues.p;
+    int32_t *counts = ctx->cur.counts;
+    unsigned long long *queues = ctx->cur.queues;
     TrialLaunch L{};
     L.cat.offsets = cat->offsets;
-    L.cat.tt = (const double *)ctx->tt.p;
-    L.cat.w = (const double *)ctx->w.p;
-    L.cat.yc = (const double *)ctx->yc.p;
-    L.cat.w32 = (const float *)ctx->w32.p;
-    L.cat.yc32 = (const float *)ctx->yc32.p;
-    L.cat.chi0 = (const double *)ctx->chi0.p;
+    L.cat.tt = ctx->cur.tt;
+    L.cat.w = ctx->cur.w;
+    L.cat.yc = ctx->cur.yc;
+    L.cat.w32 = ctx->cur.w32;
+    L.cat.yc32 = ctx->cur.yc32;
+    L.cat.chi0 = ctx->cur.chi0;
     L.cat.status = obj_status;
     L.n_tiles = n_tiles;
     L.tile_f = tile;
@@ -246,37 +323,79 @@ int trials(ss_ctx *ctx, const Plan &P, int method, const ss_catalog *cat, const 
     L.method = method;
     L.pgram64 = pgram64;
     L.pgram32 = pgram32;
-    L.part_p = want_best ? (double *)ctx->part_p.p : nullptr;
-    L.part_k = want_best ? (int32_t *)ctx->part_k.p : nullptr;
+    L.part_p = want_best ? ctx->cur.part_p : nullptr;
+    L.part_k = want_best ? ctx->cur.part_k : nullptr;
     L.ranges = ranges;
     L.pdm64 = (pdm && prm->precision == SS_FP64) ? (double *)pdm : nullptr;
     L.pdm32 = (pdm && prm->precision != SS_FP64) ? (float *)pdm : nullptr;
     L.pdm_bins = pdm_bins;
     ctx->n_timed = 0;
+    int n_launch = 0;
+    for (int c = 0; c < kNumShapes; ++c)
+        if (P.used[c] && ((P.R.runnable >> c) & 1u)) ++n_launch;
+    // several classes: fork them onto the side streams so that one class's
+    // tail overlaps the others' work (timing then covers fork to join)
+    const bool fork = n_launch > 1 && !ctx->fixed;
+    if (fork) {
+        int rc = ensure_side_streams(ctx);
+        if (rc != SS_OK) return rc;
+        if (ctx->timing) SS_HIP_TRY(hipEventRecord(ctx->ev[0], stream), "timing event");
+        SS_HIP_TRY(hipEventRecord(ctx->fork_ev, stream), "fork event");
+    }
+    int launched = 0;
     for (int c = 0; c < kNumShapes; ++c) {
         if (!P.used[c] || !((P.R.runnable >> c) & 1u)) continue;
         TrialLaunch Lc = L;
-        Lc.objs = (const int32_t *)ctx->objs.p + (int64_t)c * n_obj;
+        Lc.objs = ctx->cur.objs + (int64_t)c * n_obj;
         Lc.count = counts + c;
         Lc.queue = queues + c;
         Lc.ext = P.ext[c];
-        if (ctx->timing)
-            SS_HIP_TRY(hipEventRecord(ctx->ev[2 * ctx->n_timed], stream), "timing event");
-        SS_HIP_TRY(launch_trials(shape_id(kShapes[c].nw, kShapes[c].ppl), prm->precision, Lc,
-                                 n_obj * (int64_t)n_tiles, ctx->n_cu, stream),
-                   "trial kernel");
+        if (c == shared_class) {
+            Lc.shared_batch = shared_batch;
+            Lc.shared_n = shared_n;
+            Lc.shared_tt = shared_tt;
+        }
+        if (fork) {
+            hipStream_t sc = ctx->side[launched];
+            SS_HIP_TRY(hipStreamWaitEvent(sc, ctx->fork_ev, 0), "fork");
+            SS_HIP_TRY(launch_trials(shape_id(kShapes[c].nw, kShapes[c].ppl), prm->precision,
+                                     Lc, n_obj * (int64_t)n_tiles, ctx->n_cu, sc),
+                       "trial kernel");
+            SS_HIP_TRY(hipEventRecord(ctx->join_ev[launched], sc), "join event");
+        } else {
+            if (ctx->timing)
+                SS_HIP_TRY(hipEventRecord(ctx->ev[2 * ctx->n_timed], stream), "timing event");
+            SS_HIP_TRY(launch_trials(shape_id(kShapes[c].nw, kShapes[c].ppl), prm->precision,
+                                     Lc, n_obj * (int64_t)n_tiles, ctx->n_cu, stream),
+                       "trial kernel");
+            if (ctx->timing) {
+                SS_HIP_TRY(hipEventRecord(ctx->ev[2 * ctx->n_timed + 1], stream),
+                           "timing event");
+                ctx->n_timed++;
+            }
+        }
+        ++launched;
+    }
+    if (fork) {
+        for (int i = 0; i < launched; ++i)
+            SS_HIP_TRY(hipStreamWaitEvent(stream, ctx->join_ev[i], 0), "join");
         if (ctx->timing) {
-            SS_HIP_TRY(hipEventRecord(ctx->ev[2 * ctx->n_timed + 1], stream), "timing event");
-            ctx->n_timed++;
+            SS_HIP_TRY(hipEventRecord(ctx->ev[1], stream), "timing event");
+            ctx->n_timed = 1;
         }
     }
     if (want_best) {
-        SS_HIP_TRY(launch_finalize((const double *)ctx->part_p.p, (const int32_t *)ctx->part_k.p,
+        SS_HIP_TRY(launch_finalize(ctx->cur.part_p, ctx->cur.part_k,
                                    n_obj, n_tiles, obj_status, L.fmin, L.df, best_idx,
                                    best_period, best_power, stream),
                    "finalize kernel");
     }
     return SS_OK;
+}
+
+int32_t tile_for(const ss_ctx *ctx, int64_t n_obj, int64_t n_freq) {
+    return ctx->tile_f > 0 ? (int32_t)std::min<int64_t>(ctx->tile_f, n_freq)
+                           : choose_tile(n_obj, n_freq);
 }
 
 // Full-grid search: prep, trials over frequency tiles, finalize.
@@ -286,14 +405,70 @@ int run(ss_ctx *ctx, int method, const ss_catalog *cat, const ss_grid *grid,
         double *best_power, void *pdm = nullptr, int32_t pdm_bins = 0) {
     const int64_t n_obj = cat->n_obj;
     if (n_obj == 0) return SS_OK;
-    const int32_t tile = ctx->tile_f > 0 ? (int32_t)std::min<int64_t>(ctx->tile_f, grid->n_freq)
-                                         : choose_tile(n_obj, grid->n_freq);
+    const int32_t tile = tile_for(ctx, n_obj, grid->n_freq);
     const int32_t n_tiles = (int32_t)((grid->n_freq + tile - 1) / tile);
     Plan P;
     int rc = prepare(ctx, method, cat, prm, obj_status, stream, P);
     if (rc != SS_OK) return rc;
     return trials(ctx, P, method, cat, grid, prm, pgram64, pgram32, want_best, obj_status, stream,
                   best_idx, best_period, best_power, tile, n_tiles, nullptr, pdm, pdm_bins);
+}
+
+// Objects that share one time sampling: a CSR view (offsets o*n, built on
+// the device), prep reading the one t array, and one class launch whose
+// work items are batches of objects x frequency tiles (fold and sort once
+// per trial frequency and batch).  Objects the shape tables cannot run
+// (too long, or a shape that does not fit the LDS) take the ordinary path
+// of their class, which reports them.
+int run_shared(ss_ctx *ctx, int method, const ss_shared_catalog *sc, const ss_grid *grid,
+               const ss_params *prm, double *pgram64, float *pgram32, bool want_best,
+               int32_t *obj_status, hipStream_t stream, int64_t *best_idx, double *best_period,
+               double *best_power) {
+    const int64_t n_obj = sc->n_obj, n = sc->n_points;
+    if (n_obj == 0) return SS_OK;
+    SS_HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+    SS_HIP_TRY(ctx->sh_offsets.ensure((size_t)(n_obj + 1) * 8), "workspace");
+    SS_HIP_TRY(ctx->sh_tt.ensure((size_t)std::max<int64_t>(n, 1) * 8), "workspace");
+    SS_HIP_TRY(launch_shared_layout(sc->t, n, n_obj, (int64_t *)ctx->sh_offsets.p,
+                                    (double *)ctx->sh_tt.p, stream),
+               "shared layout kernel");
+    ss_catalog cat{n_obj, n_obj * n, (const int64_t *)ctx->sh_offsets.p, sc->t, sc->y, sc->e};
+    Plan P;
+    int rc = prepare(ctx, method, &cat, prm, obj_status, stream, P, true);
+    if (rc != SS_OK) return rc;
+    // the class every object of length n is filed in (rules first, then the
+    // defaults), as the prep kernel decides it
+    int cls = -1;
+    for (int i = 0; i < P.R.n_rules && cls < 0; ++i)
+        if (n <= P.R.rule_n[i]) cls = P.R.rule_shape[i];
+    for (int i = 0; i < P.R.n_def && cls < 0; ++i)
+        if (n <= P.R.def_n[i]) cls = P.R.def_shape[i];
+    const bool runs = cls >= 0 && n <= P.R.max_points && ((P.R.runnable >> cls) & 1u);
+    const int32_t batch = runs ? (int32_t)std::min<int64_t>(kSharedBatch, n_obj) : 0;
+    const int64_t units = runs ? (n_obj + batch - 1) / batch : n_obj;
+    const int32_t tile = ctx->tile_f > 0 ? (int32_t)std::min<int64_t>(ctx->tile_f, grid->n_freq)
+                                         : choose_tile(units, grid->n_freq);
+    const int32_t n_tiles = (int32_t)((grid->n_freq + tile - 1) / tile);
+    return trials(ctx, P, method, &cat, grid, prm, pgram64, pgram32, want_best, obj_status,
+                  stream, best_idx, best_period, best_power, tile, n_tiles, nullptr, nullptr, 0,
+                  runs ? cls : -1, batch, (int32_t)n, (const double *)ctx->sh_tt.p);
+}
+
+int check_shared(ss_ctx *ctx, const ss_shared_catalog *sc, const ss_grid *grid,
+                 const ss_params *prm) {
+    if (!sc) return fail(SS_ERR_INVALID_ARG, "null argument");
+    if (sc->n_obj < 0 || sc->n_points < 0)
+        return fail(SS_ERR_INVALID_ARG, "n_obj and n_points must be >= 0");
+    if (sc->n_obj > 0 && sc->n_points > INT64_MAX / sc->n_obj)
+        return fail(SS_ERR_INVALID_ARG, "catalog too large");
+    // offsets are built on the device; any non-null pointer passes the null check
+    ss_catalog cat{sc->n_obj, sc->n_obj * sc->n_points, (const int64_t *)sc->t, sc->t, sc->y,
+                   sc->e};
+    int rc = check_common(ctx, &cat, grid, prm);
+    if (rc != SS_OK) return rc;
+    if (sc->n_obj > 0 && sc->n_points > 0 && (!sc->t || !sc->y || !sc->e))
+        return fail(SS_ERR_INVALID_ARG, "null catalog pointer");
+    return SS_OK;
 }
 
 // First fine-grid index of each of the 1024 log-spaced bins over
@@ -342,11 +517,11 @@ EncArgs enc_args(ss_ctx *ctx, const ss_catalog *cat, const ss_grid *grid, const 
     EncArgs A{};
     A.n_obj = (int)cat->n_obj;
     A.offsets = cat->offsets;
-    A.tt = (const double *)ctx->tt.p;
-    A.yc = (const double *)ctx->yc.p;
+    A.tt = ctx->cur.tt;
+    A.yc = ctx->cur.yc;
     A.e = cat->e;
-    A.chi0 = (const double *)ctx->chi0.p;
-    A.sw = (const double *)ctx->sw.p;
+    A.chi0 = ctx->cur.chi0;
+    A.sw = ctx->cur.sw;
     A.status = status;
     A.params = params;
     feature_freqs(grid, A.g);
@@ -417,10 +592,10 @@ int bin_scores(ss_ctx *ctx, const ss_catalog *cat, const ss_grid *grid, int32_t 
     ScoreArgs A{};
     A.n_obj = (int)cat->n_obj;
     A.offsets = cat->offsets;
-    A.tt = (const double *)ctx->tt.p;
-    A.w = (const double *)ctx->w.p;
-    A.yc = (const double *)ctx->yc.p;
-    A.chi0 = (const double *)ctx->chi0.p;
+    A.tt = ctx->cur.tt;
+    A.w = ctx->cur.w;
+    A.yc = ctx->cur.yc;
+    A.chi0 = ctx->cur.chi0;
     A.status = obj_status;
     A.bin_k = (const int64_t *)ctx->bin_k.p;
     A.fmin = grid->f_min;
@@ -488,7 +663,8 @@ void ss_ctx_destroy(ss_ctx *ctx) {
     ctx->chi0.release();
     ctx->sw.release();
     for (DevBuf *b : {&ctx->emb, &ctx->act, &ctx->logits, &ctx->dlog, &ctx->loss_o, &ctx->dE,
-                      &ctx->partial, &ctx->ranges, &ctx->bin_k, &ctx->scores})
+                      &ctx->partial, &ctx->ranges, &ctx->bin_k, &ctx->scores,
+                      &ctx->sh_offsets, &ctx->sh_tt})
         b->release();
     ctx->objs.release();
     ctx->part_p.release();
@@ -497,6 +673,14 @@ void ss_ctx_destroy(ss_ctx *ctx) {
     ctx->queues.release();
     if (ctx->timing)
         for (auto &e : ctx->ev) (void)hipEventDestroy(e);
+    if (ctx->forked) {
+        for (int i = 0; i < kNumShapes; ++i) {
+            (void)hipStreamDestroy(ctx->side[i]);
+            (void)hipEventDestroy(ctx->join_ev[i]);
+        }
+        (void)hipEventDestroy(ctx->fork_ev);
+    }
+    ctx->chunk.release();
     delete ctx;
 }
 
@@ -567,6 +751,98 @@ int ss_best_period(ss_ctx *ctx, int32_t method, const ss_catalog *cat, const ss_
         return fail(SS_ERR_INVALID_ARG, "null output pointer");
     return run(ctx, method, cat, grid, params, nullptr, nullptr, true, obj_status,
                (hipStream_t)stream, best_idx, best_period, best_power);
+}
+
+int ss_shared_periodogram(ss_ctx *ctx, int32_t method, const ss_shared_catalog *cat,
+                          const ss_grid *grid, const ss_params *params, void *pgram,
+                          int32_t *obj_status, void *stream) {
+    int rc = check_shared(ctx, cat, grid, params);
+    if (rc != SS_OK) return rc;
+    if (method != SS_METHOD_SS && method != SS_METHOD_SSSP && method != SS_METHOD_SSSP_GV)
+        return fail(SS_ERR_INVALID_ARG, "method must be SS_METHOD_SS, _SSSP or _SSSP_GV");
+    if (cat->n_obj > 0 && (!pgram || !obj_status))
+        return fail(SS_ERR_INVALID_ARG, "null output pointer");
+    bool f64 = params->precision == SS_FP64;
+    return run_shared(ctx, method, cat, grid, params, f64 ? (double *)pgram : nullptr,
+                      f64 ? nullptr : (float *)pgram, false, obj_status, (hipStream_t)stream,
+                      nullptr, nullptr, nullptr);
+}
+
+int ss_shared_best_period(ss_ctx *ctx, int32_t method, const ss_shared_catalog *cat,
+                          const ss_grid *grid, const ss_params *params, int64_t *best_idx,
+                          double *best_period, double *best_power, int32_t *obj_status,
+                          void *stream) {
+    int rc = check_shared(ctx, cat, grid, params);
+    if (rc != SS_OK) return rc;
+    if (method != SS_METHOD_SS && method != SS_METHOD_SSSP && method != SS_METHOD_SSSP_GV)
+        return fail(SS_ERR_INVALID_ARG, "method must be SS_METHOD_SS, _SSSP or _SSSP_GV");
+    if (cat->n_obj > 0 && (!best_idx || !best_period || !best_power || !obj_status))
+        return fail(SS_ERR_INVALID_ARG, "null output pointer");
+    return run_shared(ctx, method, cat, grid, params, nullptr, nullptr, true, obj_status,
+                      (hipStream_t)stream, best_idx, best_period, best_power);
+}
+
+int ss_plan_batches(ss_ctx *ctx, int64_t n_obj, int64_t n_points, const ss_grid *grid,
+                    int32_t precision, int32_t want_pgram, double beta, int64_t mem_bytes,
+                    int64_t *objs_per_batch, int64_t *n_batches) {
+    if (!ctx || !objs_per_batch || !n_batches) return fail(SS_ERR_INVALID_ARG, "null argument");
+    int rc = check_grid(grid);
+    if (rc != SS_OK) return rc;
+    if (n_obj < 0 || n_points < 0) return fail(SS_ERR_INVALID_ARG, "negative size");
+    if (precision != SS_FP64 && precision != SS_FP32C)
+        return fail(SS_ERR_INVALID_ARG, "precision must be SS_FP64 or SS_FP32C");
+    if (!(beta > 0.0 && beta <= 1.0)) return fail(SS_ERR_INVALID_ARG, "beta must be in (0, 1]");
+    if (mem_bytes < 0) return fail(SS_ERR_INVALID_ARG, "mem_bytes must be >= 0");
+    double s = (double)mem_bytes;
+    if (mem_bytes == 0) {
+        SS_HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+        size_t free_b = 0, total_b = 0;
+        SS_HIP_TRY(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
+        s = (double)free_b;
+    }
+    // footprint r = fixed + n_obj * per_obj: the per-point prep workspace
+    // (tt, w, yc in FP64, w, yc in FP32) is needed once; per object the
+    // output row, the per-tile partials of the best-period reduction and the
+    // per-object arrays
+    const double fixed = 32.0 * (double)n_points;
+    const double row = want_pgram ? (double)grid->n_freq * (precision == SS_FP64 ? 8.0 : 4.0)
+                                  : 0.0;
+    const int64_t tiles = (grid->n_freq + 15) / 16;  // the smallest automatic tile
+    const double per_obj = row + 12.0 * (double)tiles + 16.0 + 4.0 * kNumShapes + 4.0;
+    const double room = beta * s - fixed;
+    if (room < per_obj)
+        return fail(SS_ERR_OOM, "not even one object fits beta times the device memory");
+    const int64_t per = (int64_t)std::min<double>(std::floor(room / per_obj),
+                                                  (double)std::max<int64_t>(n_obj, 1));
+    *objs_per_batch = per;
+    *n_batches = n_obj == 0 ? 0 : (n_obj + per - 1) / per;
+    return SS_OK;
+}
+
+int ss_periodogram_batched(ss_ctx *ctx, int32_t method, const ss_catalog *cat,
+                           const ss_grid *grid, const ss_params *params, void *chunk,
+                           int64_t chunk_objs, ss_pgram_sink sink, void *user,
+                           int32_t *obj_status, void *stream) {
+    int rc = check_common(ctx, cat, grid, params);
+    if (rc != SS_OK) return rc;
+    if (method != SS_METHOD_SS && method != SS_METHOD_SSSP && method != SS_METHOD_SSSP_GV)
+        return fail(SS_ERR_INVALID_ARG, "method must be SS_METHOD_SS, _SSSP or _SSSP_GV");
+    if (cat->n_obj > 0 && (!chunk || !sink || !obj_status || chunk_objs < 1))
+        return fail(SS_ERR_INVALID_ARG, "null chunk, sink or status, or chunk_objs < 1");
+    const hipStream_t st = (hipStream_t)stream;
+    const bool f64 = params->precision == SS_FP64;
+    for (int64_t lo = 0; lo < cat->n_obj; lo += chunk_objs) {
+        const int64_t hi = std::min(cat->n_obj, lo + chunk_objs);
+        // offsets are absolute indices into t, y, e: a batch is a window of them
+        ss_catalog sub{hi - lo, cat->n_points, cat->offsets + lo, cat->t, cat->y, cat->e};
+        rc = run(ctx, method, &sub, grid, params, f64 ? (double *)chunk : nullptr,
+                 f64 ? nullptr : (float *)chunk, false, obj_status + lo, st, nullptr, nullptr,
+                 nullptr);
+        if (rc != SS_OK) return rc;
+        SS_HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
+        sink(user, lo, hi, chunk, obj_status + lo);
+    }
+    return SS_OK;
 }
 
 int ss_num_shapes(void) { return kNumShapes; }
@@ -795,8 +1071,288 @@ int ss_bin_table(const ss_grid *grid, int64_t *first_k) {
 
 int ss_enc_num_params(void) { return kEncParams; }
 
+}  // extern "C"
+
+// ---- model object: parameters, Adam state, save / load
+
+namespace {
+
+constexpr char kModelMagic[8] = {'S', 'S', 'G', 'P', 'U', 'M', 'D', 'L'};
+constexpr uint32_t kModelFormat = 1;
+
+// Fixed little-endian header that precedes the JSON metadata and the arrays.
+struct ModelHeader {
+    char magic[8];
+    uint32_t format;
+    uint32_t json_bytes;  // JSON text follows the header
+    uint64_t n_params;
+    int32_t step;
+    float beta1, beta2, eps;
+    double f_min, f_max;
+    int64_t n_freq;
+    uint64_t array_offset;  // byte offset of params[n], then m[n], v[n] (float32)
+};
+
+bool same_grid(const ss_grid &a, const ss_grid *b) {
+    return a.f_min == b->f_min && a.f_max == b->f_max && a.n_freq == b->n_freq;
+}
+
+std::string model_json(const ss_model *m) {
+    char buf[64];
+    std::ostringstream js;
+    auto num = [&](double v) {
+        std::snprintf(buf, sizeof buf, "%.17g", v);
+        return std::string(buf);
+    };
+    double g[kEncNFreq];
+    feature_freqs(&m->grid, g);
+    js << "{\"format\": \"ssgpu-model\", \"format_version\": " << kModelFormat
+       << ", \"library_version\": " << ss_version() << ", \"n_params\": " << kEncParams
+       << ", \"layout\": [[\"W1\", 80, 64], [\"W2\", 64, 128], [\"b2\", 128], "
+          "[\"W3\", 128, 1024], [\"b3\", 1024]]"
+       << ", \"grid\": {\"f_min\": " << num(m->grid.f_min) << ", \"f_max\": "
+       << num(m->grid.f_max) << ", \"n_freq\": " << m->grid.n_freq << "}"
+       << ", \"bins\": " << kEncBins
+       << ", \"bin_edges\": \"E_b = f_min (f_max / f_min)^(b / 1024)\""
+       << ", \"feature_freqs\": [";
+    for (int i = 0; i < kEncNFreq; ++i) js << (i ? ", " : "") << num(g[i]);
+    js << "], \"step\": " << m->step << ", \"adam\": {\"beta1\": " << num(m->beta1)
+       << ", \"beta2\": " << num(m->beta2) << ", \"eps\": " << num(m->eps) << "}"
+       << ", \"arrays\": [\"params\", \"adam_m\", \"adam_v\"], \"dtype\": \"float32\"}";
+    return js.str();
+}
+
+int model_alloc(ss_model *m) {
+    const size_t bytes = (size_t)kEncParams * 4;
+    SS_HIP_TRY(hipSetDevice(m->device), "hipSetDevice");
+    SS_HIP_TRY(m->params.ensure(bytes), "model allocation");
+    SS_HIP_TRY(m->m.ensure(bytes), "model allocation");
+    SS_HIP_TRY(m->v.ensure(bytes), "model allocation");
+    SS_HIP_TRY(m->grad.ensure(bytes), "model allocation");
+    return SS_OK;
+}
+
+void model_free(ss_model *m) {
+    (void)hipSetDevice(m->device);
+    m->params.release();
+    m->m.release();
+    m->v.release();
+    m->grad.release();
+}
+
+}  // namespace
+
+extern "C" {
+
+int ss_model_create(ss_ctx *ctx, const ss_grid *grid, const float *init_params,
+                    ss_model **out) {
+    if (!ctx || !out || !init_params) return fail(SS_ERR_INVALID_ARG, "null argument");
+    *out = nullptr;
+    int rc = check_grid(grid);
+    if (rc != SS_OK) return rc;
+    ss_model *m = new ss_model();
+    m->device = ctx->device;
+    m->grid = *grid;
+    rc = model_alloc(m);
+    const size_t bytes = (size_t)kEncParams * 4;
+    if (rc == SS_OK) {
+        hipError_t e = hipMemcpy(m->params.p, init_params, bytes, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemset(m->m.p, 0, bytes);
+        if (e == hipSuccess) e = hipMemset(m->v.p, 0, bytes);
+        if (e != hipSuccess)
+            rc = fail(SS_ERR_HIP, std::string("model upload: ") + hipGetErrorString(e));
+    }
+    if (rc != SS_OK) {
+        model_free(m);
+        delete m;
+        return rc;
+    }
+    *out = m;
+    return SS_OK;
+}
+
+void ss_model_destroy(ss_model *model) {
+    if (!model) return;
+    model_free(model);
+    delete model;
+}
+
+int ss_model_info(const ss_model *model, ss_grid *grid, int32_t *step,
+                  const float **device_params) {
+    if (!model) return fail(SS_ERR_INVALID_ARG, "null model");
+    if (grid) *grid = model->grid;
+    if (step) *step = model->step;
+    if (device_params) *device_params = (const float *)model->params.p;
+    return SS_OK;
+}
+
+int ss_model_copy_params(const ss_model *model, float *dst, void *stream) {
+    if (!model || !dst) return fail(SS_ERR_INVALID_ARG, "null argument");
+    SS_HIP_TRY(hipSetDevice(model->device), "hipSetDevice");
+    SS_HIP_TRY(hipMemcpyAsync(dst, model->params.p, (size_t)kEncParams * 4,
+                              hipMemcpyDeviceToDevice, (hipStream_t)stream),
+               "parameter copy");
+    return SS_OK;
+}
+
+int ss_model_file_write(const char *path, const ss_grid *grid, int32_t step,
+                        const float *params, const float *adam_m, const float *adam_v) {
+    if (!path || !params || !adam_m || !adam_v) return fail(SS_ERR_INVALID_ARG, "null argument");
+    int rc = check_grid(grid);
+    if (rc != SS_OK) return rc;
+    if (step < 0) return fail(SS_ERR_INVALID_ARG, "step must be >= 0");
+    ss_model meta;
+    meta.grid = *grid;
+    meta.step = step;
+    const size_t n = (size_t)kEncParams;
+    const std::string js = model_json(&meta);
+    ModelHeader h{};
+    std::memcpy(h.magic, kModelMagic, 8);
+    h.format = kModelFormat;
+    h.json_bytes = (uint32_t)js.size();
+    h.n_params = n;
+    h.step = step;
+    h.beta1 = meta.beta1;
+    h.beta2 = meta.beta2;
+    h.eps = meta.eps;
+    h.f_min = grid->f_min;
+    h.f_max = grid->f_max;
+    h.n_freq = grid->n_freq;
+    h.array_offset = (sizeof(ModelHeader) + js.size() + 63) / 64 * 64;
+    std::ofstream f(path, std::ios::binary | std::ios::trunc);
+    if (!f) return fail(SS_ERR_INVALID_ARG, std::string("cannot open for writing: ") + path);
+    f.write((const char *)&h, sizeof h);
+    f.write(js.data(), (std::streamsize)js.size());
+    const std::string pad(h.array_offset - sizeof h - js.size(), '\n');
+    f.write(pad.data(), (std::streamsize)pad.size());
+    for (const float *a : {params, adam_m, adam_v}) f.write((const char *)a, (std::streamsize)(n * 4));
+    f.close();
+    if (!f) return fail(SS_ERR_INVALID_ARG, std::string("write failed: ") + path);
+    return SS_OK;
+}
+
+int ss_model_file_read(const char *path, ss_grid *grid, int32_t *step, float *params,
+                       float *adam_m, float *adam_v) {
+    if (!path || !grid || !step || !params || !adam_m || !adam_v)
+        return fail(SS_ERR_INVALID_ARG, "null argument");
+    std::ifstream f(path, std::ios::binary);
+    if (!f) return fail(SS_ERR_INVALID_ARG, std::string("cannot open: ") + path);
+    f.seekg(0, std::ios::end);
+    const uint64_t size = (uint64_t)f.tellg();
+    f.seekg(0, std::ios::beg);
+    ModelHeader h{};
+    if (size < sizeof h || !f.read((char *)&h, sizeof h))
+        return fail(SS_ERR_INVALID_ARG, "not a model file (too short)");
+    if (std::memcmp(h.magic, kModelMagic, 8) != 0)
+        return fail(SS_ERR_INVALID_ARG, "not a model file (bad magic)");
+    if (h.format != kModelFormat)
+        return fail(SS_ERR_UNSUPPORTED, "model file format " + std::to_string(h.format) +
+                                            " (this library reads " +
+                                            std::to_string(kModelFormat) + ")");
+    if (h.n_params != (uint64_t)kEncParams)
+        return fail(SS_ERR_INVALID_ARG, "model has " + std::to_string(h.n_params) +
+                                            " parameters, the encoder needs " +
+                                            std::to_string(kEncParams));
+    const uint64_t need = h.array_offset + 3ull * h.n_params * 4;
+    if (h.array_offset < sizeof h + (uint64_t)h.json_bytes || size < need)
+        return fail(SS_ERR_INVALID_ARG, "model file truncated or inconsistent");
+    ss_grid g{h.f_min, h.f_max, h.n_freq};
+    if (check_grid(&g) != SS_OK) return fail(SS_ERR_INVALID_ARG, "model file has an invalid grid");
+    if (h.step < 0 || !(h.beta1 == 0.9f && h.beta2 == 0.999f && h.eps == 1e-8f))
+        return fail(SS_ERR_INVALID_ARG, "model file has invalid optimizer state");
+    const size_t n = (size_t)h.n_params;
+    f.seekg((std::streamoff)h.array_offset, std::ios::beg);
+    for (float *a : {params, adam_m, adam_v})
+        if (!f.read((char *)a, (std::streamsize)(n * 4)))
+            return fail(SS_ERR_INVALID_ARG, "model file truncated");
+    *grid = g;
+    *step = h.step;
+    return SS_OK;
+}
+
+int ss_model_save(const ss_model *model, const char *path) {
+    if (!model || !path) return fail(SS_ERR_INVALID_ARG, "null argument");
+    const size_t n = (size_t)kEncParams;
+    std::vector<float> host(3 * n);
+    SS_HIP_TRY(hipSetDevice(model->device), "hipSetDevice");
+    SS_HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    SS_HIP_TRY(hipMemcpy(host.data(), model->params.p, n * 4, hipMemcpyDeviceToHost),
+               "model download");
+    SS_HIP_TRY(hipMemcpy(host.data() + n, model->m.p, n * 4, hipMemcpyDeviceToHost),
+               "model download");
+    SS_HIP_TRY(hipMemcpy(host.data() + 2 * n, model->v.p, n * 4, hipMemcpyDeviceToHost),
+               "model download");
+    return ss_model_file_write(path, &model->grid, model->step, host.data(), host.data() + n,
+                               host.data() + 2 * n);
+}
+
+int ss_model_load(ss_ctx *ctx, const char *path, ss_model **out) {
+    if (!ctx || !path || !out) return fail(SS_ERR_INVALID_ARG, "null argument");
+    *out = nullptr;
+    const size_t n = (size_t)kEncParams;
+    std::vector<float> host(3 * n);
+    ss_grid g{};
+    int32_t step = 0;
+    int rc = ss_model_file_read(path, &g, &step, host.data(), host.data() + n, host.data() + 2 * n);
+    if (rc != SS_OK) return rc;
+    ss_model *m = new ss_model();
+    m->device = ctx->device;
+    m->grid = g;
+    m->step = step;
+    rc = model_alloc(m);
+    if (rc == SS_OK) {
+        hipError_t e = hipMemcpy(m->params.p, host.data(), n * 4, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(m->m.p, host.data() + n, n * 4, hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(m->v.p, host.data() + 2 * n, n * 4, hipMemcpyHostToDevice);
+        if (e != hipSuccess)
+            rc = fail(SS_ERR_HIP, std::string("model upload: ") + hipGetErrorString(e));
+    }
+    if (rc != SS_OK) {
+        model_free(m);
+        delete m;
+        return rc;
+    }
+    *out = m;
+    return SS_OK;
+}
+
+int ss_train_step(ss_ctx *ctx, ss_model *model, const ss_catalog *batch, const int32_t *labels,
+                  float lr, float *loss, int32_t *obj_status, void *stream) {
+    if (!ctx || !model) return fail(SS_ERR_INVALID_ARG, "null argument");
+    if (model->device != ctx->device)
+        return fail(SS_ERR_INVALID_ARG, "model and context are on different devices");
+    if (!std::isfinite(lr)) return fail(SS_ERR_INVALID_ARG, "lr must be finite");
+    if (model->step == INT32_MAX) return fail(SS_ERR_UNSUPPORTED, "step counter exhausted");
+    int rc = ss_enc_train_grad(ctx, batch, &model->grid, (const float *)model->params.p, labels,
+                               (float *)model->grad.p, loss, obj_status, stream);
+    if (rc != SS_OK) return rc;
+    rc = ss_adam_step((float *)model->params.p, (const float *)model->grad.p,
+                      (float *)model->m.p, (float *)model->v.p, kEncParams, model->step + 1, lr,
+                      model->beta1, model->beta2, model->eps, stream);
+    if (rc != SS_OK) return rc;
+    model->step++;
+    return SS_OK;
+}
+
+int ss_best_period_learned(ss_ctx *ctx, const ss_model *model, int32_t method,
+                           const ss_catalog *cat, const ss_grid *grid, const ss_params *params,
+                           float gamma, int32_t top_k, int32_t margin, int32_t full_below,
+                           int64_t *best_idx, double *best_period, double *best_power,
+                           int32_t *obj_status, void *stream) {
+    if (!ctx || !model || !grid) return fail(SS_ERR_INVALID_ARG, "null argument");
+    if (model->device != ctx->device)
+        return fail(SS_ERR_INVALID_ARG, "model and context are on different devices");
+    if (!same_grid(model->grid, grid))
+        return fail(SS_ERR_INVALID_ARG, "the model was trained for another search grid");
+    return ss_learned_best_period(ctx, method, cat, grid, params,
+                                  (const float *)model->params.p, gamma, top_k, margin,
+                                  full_below, best_idx, best_period, best_power, obj_status,
+                                  stream);
+}
+
 const char *ss_last_error(void) { return g_last_error.c_str(); }
 
-int ss_version(void) { return 140; }
+int ss_version(void) { return 150; }
 
 }  // extern "C"

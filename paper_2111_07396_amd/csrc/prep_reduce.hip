@@ -33,7 +33,7 @@ __global__ __launch_bounds__(kWave *kPrepWaves) void prep_kernel(
     double *__restrict__ tt, double *__restrict__ w, double *__restrict__ yc,
     float *__restrict__ w32, float *__restrict__ yc32, double *__restrict__ chi0,
     double *__restrict__ sw_out, int32_t *__restrict__ status, ShapeRules rules, int32_t *__restrict__ objs,
-    int32_t *__restrict__ counts) {
+    int32_t *__restrict__ counts, int shared_t) {
     const int lane = threadIdx.x % kWave;
     const int64_t obj = (int64_t)blockIdx.x * kPrepWaves + threadIdx.x / kWave;
     if (obj >= n_obj) return;
@@ -48,7 +48,7 @@ __global__ __launch_bounds__(kWave *kPrepWaves) void prep_kernel(
         bool nonfinite = false, baderr = false;
         double tmin = __builtin_inf(), sw = 0.0, swy = 0.0;
         for (int64_t i = lane; i < n; i += kWave) {
-            const double ti = t[a + i], yi = y[a + i], ei = e[a + i];
+            const double ti = t[shared_t ? i : a + i], yi = y[a + i], ei = e[a + i];
             nonfinite |= !__builtin_isfinite(ti) || !__builtin_isfinite(yi);
             baderr |= !__builtin_isfinite(ei) || !(ei > 0.0);
             tmin = fmin(tmin, ti);
@@ -71,7 +71,7 @@ __global__ __launch_bounds__(kWave *kPrepWaves) void prep_kernel(
                 const double wi = 1.0 / (ei * ei);
                 const double d = y[a + i] - ybar;
                 acc += wi * d * d;
-                tt[a + i] = t[a + i] - tmin;
+                tt[a + i] = t[shared_t ? i : a + i] - tmin;
                 w[a + i] = wi;
                 yc[a + i] = d;
                 w32[a + i] = (float)wi;
@@ -93,6 +93,25 @@ __global__ __launch_bounds__(kWave *kPrepWaves) void prep_kernel(
         const int32_t slot = atomicAdd(&counts[cls], 1);
         objs[(int64_t)cls * n_obj + slot] = (int32_t)obj;
     }
+}
+
+// Shared time sampling: CSR offsets o*n for the n_obj objects and the times
+// relative to their minimum (non-finite times are left for the prep status).
+__global__ __launch_bounds__(256) void shared_layout_kernel(const double *__restrict__ t,
+                                                            int64_t n, int64_t n_obj,
+                                                            int64_t *__restrict__ offsets,
+                                                            double *__restrict__ shared_tt) {
+    __shared__ double part[256 / kWave];
+    const int tid = threadIdx.x;
+    for (int64_t o = tid; o <= n_obj; o += 256) offsets[o] = o * n;
+    double m = __builtin_inf();
+    for (int64_t i = tid; i < n; i += 256) m = fmin(m, t[i]);
+    m = wave_min(m);
+    if (tid % kWave == 0) part[tid / kWave] = m;
+    __syncthreads();
+    double tmin = part[0];
+    for (int w = 1; w < 256 / kWave; ++w) tmin = fmin(tmin, part[w]);
+    for (int64_t i = tid; i < n; i += 256) shared_tt[i] = t[i] - tmin;
 }
 
 // One thread per object: first maximum over the tiles in frequency order,
@@ -140,12 +159,20 @@ hipError_t launch_reset(int32_t *counts, unsigned long long *queues, int n, hipS
 hipError_t launch_prep(const int64_t *offsets, const double *t, const double *y, const double *e,
                        int64_t n_obj, int64_t n_points, double *tt, double *w, double *yc, float *w32, float *yc32,
                        double *chi0, double *sw, int32_t *status, const ShapeRules &rules,
-                       int32_t *objs, int32_t *counts, hipStream_t stream) {
+                       int32_t *objs, int32_t *counts, hipStream_t stream, bool shared_t) {
     if (n_obj <= 0) return hipSuccess;
     const int64_t blocks = (n_obj + kPrepWaves - 1) / kPrepWaves;
     hipLaunchKernelGGL(prep_kernel, dim3((unsigned)blocks), dim3(kWave * kPrepWaves), 0, stream,
                        offsets, t, y, e, n_obj, n_points, tt, w, yc, w32, yc32, chi0, sw, status,
-                       rules, objs, counts);
+                       rules, objs, counts, shared_t ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_shared_layout(const double *t, int64_t n, int64_t n_obj, int64_t *offsets,
+                                double *shared_tt, hipStream_t stream) {
+    if (n_obj <= 0) return hipSuccess;
+    hipLaunchKernelGGL(shared_layout_kernel, dim3(1), dim3(256), 0, stream, t, n, n_obj, offsets,
+                       shared_tt);
     return hipGetLastError();
 }
 

@@ -43,7 +43,14 @@ struct TrialLaunch {
     double *pdm64;          // phase-dispersion periodogram [n_obj * n_freq] or null
     float *pdm32;
     int32_t pdm_bins;       // phase bins (0: clamp(n / 5, 4, 32))
+    // shared time sampling: work items are (batch of shared_batch objects of
+    // the class, tile); every object has shared_n points observed at the
+    // times whose prepared form is shared_tt.  shared_batch = 0: off.
+    int32_t shared_batch;
+    int32_t shared_n;
+    const double *shared_tt;
 };
+constexpr int kMaxSharedBatch = 16;
 
 // Expressions that must round exactly like their plain C statement (no
 // fused multiply-add), so that grid frequencies, window half-widths and the
@@ -104,7 +111,12 @@ hipError_t launch_reset(int32_t *counts, unsigned long long *queues, int n, hipS
 hipError_t launch_prep(const int64_t *offsets, const double *t, const double *y, const double *e,
                        int64_t n_obj, int64_t n_points, double *tt, double *w, double *yc, float *w32, float *yc32,
                        double *chi0, double *sw, int32_t *status, const ShapeRules &rules,
-                       int32_t *objs, int32_t *counts, hipStream_t stream);
+                       int32_t *objs, int32_t *counts, hipStream_t stream,
+                       bool shared_t = false);
+
+// Shared time sampling: offsets[o] = o*n (o <= n_obj) and shared_tt = t - min t.
+hipError_t launch_shared_layout(const double *t, int64_t n, int64_t n_obj, int64_t *offsets,
+                                double *shared_tt, hipStream_t stream);
 
 // Persistent launch of one class: grid = co-resident workgroups (at most
 // max_items).

@@ -18,10 +18,8 @@
 //   phase A1: prefix of w, w x, w x^2 -> geometry of every span;
 //   phase A2: prefix of w y, w x y    -> the cross-validated smooths of y;
 //   phase B:  one prefix pair per later smooth (residuals, spans, blend).
-// Three prefix arrays are live at a time (four where the phase-B pairs are
-// double-buffered, see double_buffered).  With PPL even, the arrays get one
-// pad slot per PPL slots so that the threads' reads at a common offset fall
-// in distinct LDS banks.
+// The prefixes of one slot are stored together (F values per slot, see
+// qaddr), so that one LDS address serves every prefix a window end needs.
 #pragma once
 #include "numeric.hpp"
 #include "ssgpu_internal.hpp"
@@ -31,9 +29,21 @@ namespace ssg {
 namespace {
 
 // ------------------------------------------------------------------ layout
-template <int PPL>
-__device__ __forceinline__ int phys(int u) {
-    return (PPL % 2 == 0) ? u + u / PPL : u;
+// Prefix storage: slot u holds F consecutive values: the x-moment prefixes
+// (W, X, XX) in fields 0..2 during the geometry phase, then a prefix pair
+// (V, XV) in fields 0, 1 and, for double-buffered groups (F = 4), a second
+// pair in fields 2, 3.  A window end is then one address with constant
+// offsets (paired 16-byte loads) instead of one address per prefix array.
+// After every PPL slots come pad_q values: the 64 lanes read at a common
+// offset from their own PPL consecutive slots, and the pad makes the lane
+// stride an odd number of 8-byte words (F = 3) or of 16-byte words (F = 4),
+// so that the lanes of one LDS cycle fall in distinct banks.
+constexpr __host__ __device__ int pad_q(int f, int ppl) {
+    return f == 4 ? 2 : (ppl % 2 == 0 ? 1 : 0);
+}
+template <int F, int PPL>
+__device__ __forceinline__ int qaddr(int u) {
+    return u * F + (u / PPL) * pad_q(F, PPL);
 }
 
 // Groups of up to 1,024 points keep the work item's object (t, y, w) in LDS
@@ -43,7 +53,8 @@ constexpr __host__ __device__ bool caches_object(int np) { return np <= 1024; }
 
 // Prefix arrays of a trial group.  The SS kernels of multi-wavefront groups
 // that cache the object alternate their later smooths between two prefix
-// pairs, (A0, A1) and (A2, A3): a pass then needs no barrier before it
+// pairs, fields (0, 1) and (2, 3) of the prefix slots: a pass then needs no
+// barrier before it
 // writes, as the pair it overwrites was last read two passes earlier, behind
 // that pass's barriers (measured: +3-7 % on these kernels; a single
 // wavefront's barrier is only a wait on its own LDS operations, and there the
@@ -55,23 +66,27 @@ constexpr __host__ __device__ int prefix_arrays(int method, int nw, int ppl) {
     return double_buffered(method, nw, ppl) ? 4 : 3;
 }
 
-// LDS layout of one trial group; identical on host and device.
+// LDS layout of one trial group; identical on host and device.  The prefix
+// region starts at 0 and also serves as scratch of three arrays of np values
+// (tie averaging, CV fallbacks), and as the sort's counters and keys.
 struct Layout {
-    int np, ext, slots, arr, sk, xch, qslot, obj, bytes;
+    int np, ext, F, qbytes, sk, xch, qslot, best, obj, bytes;
     __host__ __device__ Layout(int nw, int ppl, int ext_, int method) {
         np = kWave * nw * ppl;
         ext = ext_;
+        F = prefix_arrays(method, nw, ppl);
         const bool cache = caches_object(np);
         const int ulen = np + 2 * ext + 1;
-        slots = (ppl % 2 == 0) ? ulen + ulen / ppl + 1 : ulen;
-        arr = (slots * 8 + 15) / 16 * 16;
+        int nd = (ulen - 1) * F + ((ulen - 1) / ppl) * pad_q(F, ppl) + F;  // values
+        if (nd < 3 * np) nd = 3 * np;
+        qbytes = (nd * 8 + 15) / 16 * 16;
         const int sort_end = ((np + 1) * 4 + 15) / 16 * 16 + (cache ? 1 : 3) * np * 8;
-        const int narr = prefix_arrays(method, nw, ppl);
-        int a = narr * arr > sort_end ? narr * arr : sort_end;
+        int a = qbytes > sort_end ? qbytes : sort_end;
         sk = (a + 15) / 16 * 16;
         xch = sk + np * 8;
         qslot = xch + nw * 8 * 8;
-        obj = qslot + 16;
+        best = qslot + 16;
+        obj = best + kMaxSharedBatch * 12;
         bytes = obj + (cache ? 3 * np * 8 : 0);
     }
 };
@@ -85,12 +100,11 @@ __device__ __forceinline__ void bsync() {
     }
 }
 
-template <class P, int NW, int PPL>
+template <class P, int NW, int PPL, int F>
 struct Group {
     using S = typename P::S;
     static constexpr int NT = kWave * NW;
-    S *A0, *A1, *A2;         // prefix arrays (or scratch)
-    S *A3;                   // second pair's second array (double-buffered SS)
+    S *Q;                    // interleaved prefix storage (or scratch)
     const uint64_t *SK;      // sorted keys
     S *xs;                   // exchange slots for group scans
     double *xd;              // exchange slots for group sums
@@ -98,7 +112,11 @@ struct Group {
     double vsmlsq;
     double inv_n, inv_chi0;  // 1/n and 1/chi0 of the work item's object
     bool ties;
-    __device__ int slot(int i) const { return phys<PPL>(ext + i); }
+    // first value of prefix slot i (i = -ext .. n + ext)
+    __device__ int at(int i) const { return qaddr<F, PPL>(ext + i); }
+    // scratch array k (0..2) of NT * PPL values of type R
+    template <class R>
+    __device__ R *scratch(int k) const { return (R *)Q + k * (NT * PPL); }
 };
 
 // Half-window of a span: b = max(2, floor(0.5*span*n + 0.5)), clamped so
@@ -126,8 +144,8 @@ __device__ __forceinline__ typename P::R bass_pow(typename P::R tmp, typename P:
 
 // ------------------------------------------------------------------ group reductions
 // Sum over the group of two doubles, identical in every thread.
-template <class P, int NW, int PPL>
-__device__ __forceinline__ void group_sum2(const Group<P, NW, PPL> &G, double &a, double &b) {
+template <class P, int NW, int PPL, int F>
+__device__ __forceinline__ void group_sum2(const Group<P, NW, PPL, F> &G, double &a, double &b) {
     a = wave_sum(a);
     b = wave_sum(b);
     if constexpr (NW > 1) {
@@ -147,8 +165,8 @@ __device__ __forceinline__ void group_sum2(const Group<P, NW, PPL> &G, double &a
 }
 
 // Exclusive prefix over the group's threads of M values; also the totals.
-template <class P, int NW, int PPL, int M>
-__device__ __forceinline__ void group_excl(const Group<P, NW, PPL> &G,
+template <class P, int NW, int PPL, int M, int F>
+__device__ __forceinline__ void group_excl(const Group<P, NW, PPL, F> &G,
                                            const typename P::S (&tot)[M],
                                            typename P::S (&excl)[M], typename P::S (&all)[M]) {
     using S = typename P::S;
@@ -191,8 +209,8 @@ __device__ __forceinline__ void group_excl(const Group<P, NW, PPL> &G,
 //   left:  P(-k) = P(n-k) - T  with the copy's phase shifted by -1,
 // so that X and XX pick up the terms of (x +- 1) and (x +- 1)^2.  Slots past
 // n + e are left unwritten (no window reaches them).
-template <class P, int NW, int PPL, int M, bool EXT>
-__device__ __forceinline__ void build_prefix(const Group<P, NW, PPL> &G,
+template <class P, int NW, int PPL, int M, bool EXT, int F>
+__device__ __forceinline__ void build_prefix(const Group<P, NW, PPL, F> &G,
                                              typename P::S *const (&Pf)[M],
                                              const typename P::S (&v)[M][PPL],
                                              typename P::S (&T)[M], int e = 0) {
@@ -220,11 +238,11 @@ __device__ __forceinline__ void build_prefix(const Group<P, NW, PPL> &G,
         for (int m = 0; m < M; ++m) val[m] = P::add(excl[m], loc[m][p]);
         if (!EXT || u <= n) {
 #pragma unroll
-            for (int m = 0; m < M; ++m) Pf[m][G.slot(u)] = val[m];
+            for (int m = 0; m < M; ++m) Pf[m][G.at(u)] = val[m];
         }
         if constexpr (EXT) {
             if (u <= e && u <= n) {  // right copy, k = u
-                const int d = G.slot(n + u);
+                const int d = G.at(n + u);
                 if constexpr (M == 3) {
                     Pf[0][d] = P::add(T[0], val[0]);
                     Pf[1][d] = P::add(P::add(T[1], val[1]), val[0]);
@@ -235,7 +253,7 @@ __device__ __forceinline__ void build_prefix(const Group<P, NW, PPL> &G,
                 }
             }
             if (u < n && u >= n - e) {  // left copy, k = n - u
-                const int d = G.slot(u - n);
+                const int d = G.at(u - n);
                 if constexpr (M == 3) {
                     const S rw = P::sub(T[0], val[0]);
                     const S rx = P::sub(T[1], val[1]);
@@ -254,7 +272,7 @@ __device__ __forceinline__ void build_prefix(const Group<P, NW, PPL> &G,
     }
     if (G.t == 0) {
 #pragma unroll
-        for (int m = 0; m < M; ++m) Pf[m][G.slot(0)] = P::zero();
+        for (int m = 0; m < M; ++m) Pf[m][G.at(0)] = P::zero();
     }
     bsync<NW>();
 }
@@ -262,25 +280,25 @@ __device__ __forceinline__ void build_prefix(const Group<P, NW, PPL> &G,
 // Periodic extension of the x-moment prefix (W, X, XX) by e slots per side.
 // Right: P(n+k) = T + P(k) with the copy's phase shifted by +1.
 // Left:  P(-k) = P(n-k) - T with the copy's phase shifted by -1.
-template <class P, int NW, int PPL>
-__device__ __forceinline__ void extend3(const Group<P, NW, PPL> &G, typename P::S *W,
+template <class P, int NW, int PPL, int F>
+__device__ __forceinline__ void extend3(const Group<P, NW, PPL, F> &G, typename P::S *W,
                                         typename P::S *X, typename P::S *XX,
                                         const typename P::S (&T)[3], int e) {
     const int n = G.n;
-    for (int q = G.t; q < 2 * e; q += Group<P, NW, PPL>::NT) {
+    for (int q = G.t; q < 2 * e; q += Group<P, NW, PPL, F>::NT) {
         if (q < e) {
             const int k = q + 1;
-            const auto pw = W[G.slot(k)], px = X[G.slot(k)], pxx = XX[G.slot(k)];
-            const int d = G.slot(n + k);
+            const auto pw = W[G.at(k)], px = X[G.at(k)], pxx = XX[G.at(k)];
+            const int d = G.at(n + k);
             W[d] = P::add(T[0], pw);
             X[d] = P::add(P::add(T[1], px), pw);
             XX[d] = P::add(P::add(T[2], pxx), P::add(P::twice(px), pw));
         } else {
             const int k = q - e + 1;
-            const auto rw = P::sub(T[0], W[G.slot(n - k)]);
-            const auto rx = P::sub(T[1], X[G.slot(n - k)]);
-            const auto rxx = P::sub(T[2], XX[G.slot(n - k)]);
-            const int d = G.slot(-k);
+            const auto rw = P::sub(T[0], W[G.at(n - k)]);
+            const auto rx = P::sub(T[1], X[G.at(n - k)]);
+            const auto rxx = P::sub(T[2], XX[G.at(n - k)]);
+            const int d = G.at(-k);
             W[d] = P::neg(rw);
             X[d] = P::sub(rw, rx);
             XX[d] = P::neg(P::add(P::sub(rxx, P::twice(rx)), rw));
@@ -290,22 +308,22 @@ __device__ __forceinline__ void extend3(const Group<P, NW, PPL> &G, typename P::
 }
 
 // Same for a prefix pair (V, XV) of w v and w x v.
-template <class P, int NW, int PPL>
-__device__ __forceinline__ void extend2(const Group<P, NW, PPL> &G, typename P::S *V,
+template <class P, int NW, int PPL, int F>
+__device__ __forceinline__ void extend2(const Group<P, NW, PPL, F> &G, typename P::S *V,
                                         typename P::S *XV, const typename P::S (&T)[2], int e) {
     const int n = G.n;
-    for (int q = G.t; q < 2 * e; q += Group<P, NW, PPL>::NT) {
+    for (int q = G.t; q < 2 * e; q += Group<P, NW, PPL, F>::NT) {
         if (q < e) {
             const int k = q + 1;
-            const auto pv = V[G.slot(k)], pxv = XV[G.slot(k)];
-            const int d = G.slot(n + k);
+            const auto pv = V[G.at(k)], pxv = XV[G.at(k)];
+            const int d = G.at(n + k);
             V[d] = P::add(T[0], pv);
             XV[d] = P::add(P::add(T[1], pxv), pv);
         } else {
             const int k = q - e + 1;
-            const auto rv = P::sub(T[0], V[G.slot(n - k)]);
-            const auto rxv = P::sub(T[1], XV[G.slot(n - k)]);
-            const int d = G.slot(-k);
+            const auto rv = P::sub(T[0], V[G.at(n - k)]);
+            const auto rxv = P::sub(T[1], XV[G.at(n - k)]);
+            const int d = G.at(-k);
             V[d] = P::neg(rv);
             XV[d] = P::sub(rv, rxv);
         }
@@ -326,11 +344,12 @@ constexpr bool fused_extension() {
     return F64 && (PPL == 1 || (PPL == 2 && NW > 1));
 }
 
-// Prefix pair of w v and w x v, extended by e.  BUF 0: into (A0, A1) after a
-// barrier; BUF 1: into (A2, A3), BUF 2: into (A0, A1), both without one
+// Prefix pair of w v and w x v, extended by e.  BUF 0: into fields (0, 1)
+// after a barrier; BUF 1: into fields (2, 3), BUF 2: into (0, 1), both
+// without one
 // (double-buffered passes).
-template <class P, int NW, int PPL, int BUF = 0>
-__device__ __forceinline__ void prefix_pair(const Group<P, NW, PPL> &G,
+template <class P, int NW, int PPL, int BUF = 0, int F>
+__device__ __forceinline__ void prefix_pair(const Group<P, NW, PPL, F> &G,
                                             const typename P::R (&w)[PPL],
                                             const typename P::S (&wx)[PPL],
                                             const typename P::R (&v)[PPL], int e) {
@@ -341,8 +360,8 @@ __device__ __forceinline__ void prefix_pair(const Group<P, NW, PPL> &G,
         q[0][p] = P::prod(w[p], v[p]);
         q[1][p] = P::mulr(wx[p], v[p]);
     }
-    S *const V = BUF == 1 ? G.A2 : G.A0;
-    S *const XV = BUF == 1 ? G.A3 : G.A1;
+    S *const V = G.Q + (BUF == 1 ? 2 : 0);
+    S *const XV = V + 1;
     S *const Pf[2] = {V, XV};
     S T[2];
     if constexpr (BUF == 0) bsync<NW>();
@@ -354,19 +373,21 @@ __device__ __forceinline__ void prefix_pair(const Group<P, NW, PPL> &G,
     }
 }
 
-template <class P, int NW, int PPL>
-__device__ __forceinline__ typename P::Geo geometry(const Group<P, NW, PPL> &G, int j, int b,
+template <class P, int NW, int PPL, int F>
+__device__ __forceinline__ typename P::Geo geometry(const Group<P, NW, PPL, F> &G, int j, int b,
                                                     typename P::S xj, typename P::R &h) {
-    const int hi = G.slot(j + b + 1), lo = G.slot(j - b);
-    return P::geo(P::sub(G.A0[hi], G.A0[lo]), P::sub(G.A1[hi], G.A1[lo]),
-                  P::sub(G.A2[hi], G.A2[lo]), xj, G.vsmlsq, h);
+    const int hi = G.at(j + b + 1), lo = G.at(j - b);
+    const typename P::S *Q = G.Q;
+    return P::geo(P::sub(Q[hi], Q[lo]), P::sub(Q[hi + 1], Q[lo + 1]), P::sub(Q[hi + 2], Q[lo + 2]),
+                  xj, G.vsmlsq, h);
 }
 
-template <class P, int NW, int PPL>
-__device__ __forceinline__ typename P::R window_fit(const Group<P, NW, PPL> &G,
+template <class P, int NW, int PPL, int F>
+__device__ __forceinline__ typename P::R window_fit(const Group<P, NW, PPL, F> &G,
                                                     const typename P::Geo &g, int j, int b) {
-    const int hi = G.slot(j + b + 1), lo = G.slot(j - b);
-    return P::eval(g, P::sub(G.A0[hi], G.A0[lo]), P::sub(G.A1[hi], G.A1[lo]));
+    const int hi = G.at(j + b + 1), lo = G.at(j - b);
+    const typename P::S *Q = G.Q;
+    return P::eval(g, P::sub(Q[hi], Q[lo]), P::sub(Q[hi + 1], Q[lo + 1]));
 }
 
 // ------------------------------------------------------------------ rare paths
@@ -411,13 +432,14 @@ __device__ __noinline__ void fallback_fill(const R *r, R *out, int j0, int j1) {
     }
 }
 
-// Replaces s over every run of equal phase by the run's weighted mean (A0..A2
-// are used as scratch and must be dead).
-template <class P, int NW, int PPL>
-__device__ void tie_average(const Group<P, NW, PPL> &G, const typename P::R (&w)[PPL],
+// Replaces s over every run of equal phase by the run's weighted mean (the
+// prefix storage is used as scratch and must be dead).
+template <class P, int NW, int PPL, int F>
+__device__ void tie_average(const Group<P, NW, PPL, F> &G, const typename P::R (&w)[PPL],
                             typename P::R (&s)[PPL]) {
     using R = typename P::R;
-    R *S1 = (R *)G.A0, *S2 = (R *)G.A1, *S3 = (R *)G.A2;
+    R *S1 = G.template scratch<R>(0), *S2 = G.template scratch<R>(1),
+      *S3 = G.template scratch<R>(2);
     bsync<NW>();
 #pragma unroll
     for (int p = 0; p < PPL; ++p) {
@@ -448,12 +470,12 @@ __device__ __forceinline__ typename P::R cv_resid(typename P::R v, typename P::R
 }
 
 // Where 1 - w h <= 0 the residual repeats the previous point's (0 at j = 0).
-// Uses A1, A2 as scratch.  `any` must be uniform over the group.
-template <class P, int NW, int PPL>
-__device__ void cv_fallback(const Group<P, NW, PPL> &G, bool any, typename P::R (&r)[PPL]) {
+// Uses the prefix storage as scratch.  `any` must be uniform over the group.
+template <class P, int NW, int PPL, int F>
+__device__ void cv_fallback(const Group<P, NW, PPL, F> &G, bool any, typename P::R (&r)[PPL]) {
     using R = typename P::R;
     if (!any) return;
-    R *S1 = (R *)G.A1, *S2 = (R *)G.A2;
+    R *S1 = G.template scratch<R>(1), *S2 = G.template scratch<R>(2);
     bsync<NW>();
 #pragma unroll
     for (int p = 0; p < PPL; ++p) {
@@ -472,8 +494,8 @@ __device__ void cv_fallback(const Group<P, NW, PPL> &G, bool any, typename P::R 
 }
 
 // Whether any point has a negative (marked) residual in any of three arrays.
-template <class P, int NW, int PPL>
-__device__ __forceinline__ bool group_any_neg3(const Group<P, NW, PPL> &G,
+template <class P, int NW, int PPL, int F>
+__device__ __forceinline__ bool group_any_neg3(const Group<P, NW, PPL, F> &G,
                                                const typename P::R (&r0)[PPL],
                                                const typename P::R (&r1)[PPL],
                                                const typename P::R (&r2)[PPL]) {
@@ -490,8 +512,8 @@ __device__ __forceinline__ bool group_any_neg3(const Group<P, NW, PPL> &G,
 }
 
 // Whether any point of the group has a negative (marked) residual.
-template <class P, int NW, int PPL>
-__device__ __forceinline__ bool group_any_neg(const Group<P, NW, PPL> &G,
+template <class P, int NW, int PPL, int F>
+__device__ __forceinline__ bool group_any_neg(const Group<P, NW, PPL, F> &G,
                                               const typename P::R (&r)[PPL]) {
     bool bad = false;
 #pragma unroll
@@ -505,8 +527,8 @@ __device__ __forceinline__ bool group_any_neg(const Group<P, NW, PPL> &G,
 
 // Weighted residual sum, accumulated per thread in the policy's sum type and
 // reduced across the group in FP64.
-template <class P, int NW, int PPL>
-__device__ __forceinline__ double chi2_of(const Group<P, NW, PPL> &G,
+template <class P, int NW, int PPL, int F>
+__device__ __forceinline__ double chi2_of(const Group<P, NW, PPL, F> &G,
                                           const typename P::R (&w)[PPL],
                                           const typename P::R (&y)[PPL],
                                           const typename P::R (&smo)[PPL]) {
@@ -524,28 +546,28 @@ __device__ __forceinline__ double chi2_of(const Group<P, NW, PPL> &G,
 
 // Smooth of v with a stored geometry (phase B): prefix pair (BUF as in
 // prefix_pair), fit, ties.
-template <class P, int NW, int PPL, int BUF = 0>
-__device__ __forceinline__ void smooth_with(const Group<P, NW, PPL> &G, int b,
+template <class P, int NW, int PPL, int BUF = 0, int F>
+__device__ __forceinline__ void smooth_with(const Group<P, NW, PPL, F> &G, int b,
                                            const typename P::Geo (&g)[PPL],
                                            const typename P::R (&w)[PPL],
                                            const typename P::S (&wx)[PPL],
                                            const typename P::R (&v)[PPL], int e,
                                            typename P::R (&s)[PPL]) {
     prefix_pair<P, NW, PPL, BUF>(G, w, wx, v, e);
-    const typename P::S *V = BUF == 1 ? G.A2 : G.A0;
-    const typename P::S *XV = BUF == 1 ? G.A3 : G.A1;
+    const typename P::S *V = G.Q + (BUF == 1 ? 2 : 0);
+    const typename P::S *XV = V + 1;
 #pragma unroll
     for (int p = 0; p < PPL; ++p) {
         const int j = min(G.t * PPL + p, G.n - 1);
-        const int hi = G.slot(j + b + 1), lo = G.slot(j - b);
+        const int hi = G.at(j + b + 1), lo = G.at(j - b);
         s[p] = P::eval(g[p], P::sub(V[hi], V[lo]), P::sub(XV[hi], XV[lo]));
     }
     if (G.ties) tie_average<P, NW, PPL>(G, w, s);
 }
 
 // Phase A1: prefix of the x-moments, extended by e.
-template <class P, int NW, int PPL>
-__device__ __forceinline__ void prefix_x(const Group<P, NW, PPL> &G,
+template <class P, int NW, int PPL, int F>
+__device__ __forceinline__ void prefix_x(const Group<P, NW, PPL, F> &G,
                                          const typename P::S (&x)[PPL],
                                          const typename P::R (&w)[PPL],
                                          const typename P::S (&wx)[PPL], int e) {
@@ -557,20 +579,20 @@ __device__ __forceinline__ void prefix_x(const Group<P, NW, PPL> &G,
         q[1][p] = wx[p];
         q[2][p] = P::mul(wx[p], x[p]);
     }
-    S *const Pf[3] = {G.A0, G.A1, G.A2};
+    S *const Pf[3] = {G.Q, G.Q + 1, G.Q + 2};
     S T[3];
     bsync<NW>();
     if constexpr (fused_extension<P::kIsF64, NW, PPL>()) {
         build_prefix<P, NW, PPL, 3, true>(G, Pf, q, T, e);
     } else {
         build_prefix<P, NW, PPL, 3, false>(G, Pf, q, T);
-        extend3<P, NW, PPL>(G, G.A0, G.A1, G.A2, T, e);
+        extend3<P, NW, PPL>(G, G.Q, G.Q + 1, G.Q + 2, T, e);
     }
 }
 
 // ------------------------------------------------------------------ Listing 1
-template <class P, int NW, int PPL>
-__device__ double supersmoother(const Group<P, NW, PPL> &G, const TrialLaunch &L,
+template <class P, int NW, int PPL, int F>
+__device__ double supersmoother(const Group<P, NW, PPL, F> &G, const TrialLaunch &L,
                                 const typename P::S (&x)[PPL], const typename P::R (&w)[PPL],
                                 const typename P::S (&wx)[PPL], const typename P::R (&y)[PPL]) {
     using R = typename P::R;
@@ -703,8 +725,8 @@ __device__ double supersmoother(const Group<P, NW, PPL> &G, const TrialLaunch &L
 // point by the un-smoothed generalized-validation residual
 // |y - s_k| / (1 - TR_k/n), Listing 1's scan, bass enhancement, clip and
 // blend of the s_k, chi^2 of the blend (no residual, span or final smooth).
-template <class P, int NW, int PPL, bool GV>
-__device__ double single_pass(const Group<P, NW, PPL> &G, const TrialLaunch &L,
+template <class P, int NW, int PPL, bool GV, int F>
+__device__ double single_pass(const Group<P, NW, PPL, F> &G, const TrialLaunch &L,
                               const typename P::S (&x)[PPL], const typename P::R (&w)[PPL],
                               const typename P::S (&wx)[PPL], const typename P::R (&y)[PPL]) {
     using R = typename P::R;
@@ -842,8 +864,8 @@ __device__ __forceinline__ int count_below(const uint64_t *SK, int n, uint64_t b
 // with b 2^48 <= B phase48 < (b + 1) 2^48, a contiguous run found by binary
 // search on the sorted keys; its sums are differences of prefix sums of w and
 // w y built in A0, A1 (free until the smoother starts).
-template <class P, int NW, int PPL>
-__device__ double pdm_score(const Group<P, NW, PPL> &G, int B, const typename P::R (&w)[PPL],
+template <class P, int NW, int PPL, int F>
+__device__ double pdm_score(const Group<P, NW, PPL, F> &G, int B, const typename P::R (&w)[PPL],
                             const typename P::R (&y)[PPL], double chi0) {
     using S = typename P::S;
     S q[2][PPL];
@@ -852,21 +874,21 @@ __device__ double pdm_score(const Group<P, NW, PPL> &G, int B, const typename P:
         q[0][p] = P::from(w[p]);
         q[1][p] = P::prod(w[p], y[p]);
     }
-    S *const Pf[2] = {G.A0, G.A1};
+    S *const Pf[2] = {G.Q, G.Q + 1};
     S T[2];
     bsync<NW>();
     build_prefix<P, NW, PPL, 2, false>(G, Pf, q, T);
     const int n = G.n;
     const uint64_t one = 1ull << 48;
     double e = 0.0, z = 0.0;
-    for (int b = G.t; b < B; b += Group<P, NW, PPL>::NT) {
+    for (int b = G.t; b < B; b += Group<P, NW, PPL, F>::NT) {
         const int lo = count_below(G.SK, n, ((uint64_t)b * one + (uint64_t)(B - 1)) / (uint64_t)B);
         const int hi = b == B - 1 ? n
                                   : count_below(G.SK, n,
                                                 ((uint64_t)(b + 1) * one + (uint64_t)(B - 1)) /
                                                     (uint64_t)B);
-        const double wb = P::dbl(P::sub(G.A0[G.slot(hi)], G.A0[G.slot(lo)]));
-        const double sb = P::dbl(P::sub(G.A1[G.slot(hi)], G.A1[G.slot(lo)]));
+        const double wb = P::dbl(P::sub(G.Q[G.at(hi)], G.Q[G.at(lo)]));
+        const double sb = P::dbl(P::sub(G.Q[G.at(hi) + 1], G.Q[G.at(lo) + 1]));
         if (wb > 0.0) e += sb * sb / wb;
     }
     group_sum2<P, NW, PPL>(G, e, z);
@@ -882,24 +904,22 @@ struct ObjData {
     const typename P::R *y, *w;
 };
 
-template <class P, int NW, int PPL, int METHOD, bool PDM>
-__device__ double run_trial(Group<P, NW, PPL> &G, unsigned char *lds, const Layout &Y,
-                            const TrialLaunch &L, const ObjData<P> &od, double f, double chi0,
-                            double &pdm) {
-    using R = typename P::R;
-    using S = typename P::S;
+// Fold (FP64) and stable sort of one trial frequency: the sorted keys in SK
+// (48-bit phase, point index in the low 16 bits), G.ties, G.vsmlsq.  Needs
+// only the times, so objects that share them share this step.  Returns true
+// when the sorted phases do not spread (Listing 1's constant fit).
+template <class P, int NW, int PPL, bool CACHE_TT, int F>
+__device__ bool fold_sort(Group<P, NW, PPL, F> &G, unsigned char *lds, const Layout &Y,
+                          const double *tt_global, double f) {
     const int n = G.n, t = G.t, NP = Y.np;
-    constexpr bool kCache = caches_object(kWave * NW * PPL);
-    const double *ct = (const double *)(lds + Y.obj);  // object cache (kCache)
-    const R *cy = (const R *)(lds + Y.obj + NP * 8);
-    const R *cw = (const R *)(lds + Y.obj + 2 * NP * 8);
+    const double *ct = (const double *)(lds + Y.obj);  // cached times (CACHE_TT)
     // ---- fold (FP64): phase = frac(tt*f), as a 48-bit fixed-point key with
     // the point index in the low 16 bits (stable order on equal phases)
     uint64_t key[PPL];
 #pragma unroll
     for (int p = 0; p < PPL; ++p) {
         const int j = t * PPL + p;
-        const double x = (kCache ? ct : od.tt)[min(j, n - 1)];
+        const double x = (CACHE_TT ? ct : tt_global)[min(j, n - 1)];
         // fraction of the exact product tt f (one rounding, the same for every
         // point); clamped at 0 where tt f lies just below an integer that its
         // rounded value reached, so that ph is always in [0, 1)
@@ -915,8 +935,6 @@ __device__ double run_trial(Group<P, NW, PPL> &G, unsigned char *lds, const Layo
     // a bucket by comparing against its (few) members.
     uint32_t *cnt = (uint32_t *)lds;
     uint64_t *tmp = (uint64_t *)(lds + ((NP + 1) * 4 + 15) / 16 * 16);
-    R *sy = (R *)(tmp + NP);
-    R *sw = (R *)(tmp + 2 * NP);
     uint64_t *SK = (uint64_t *)(lds + Y.sk);
     bsync<NW>();
 #pragma unroll
@@ -952,7 +970,7 @@ __device__ double run_trial(Group<P, NW, PPL> &G, unsigned char *lds, const Layo
             cnt[t * PPL + p] = run;
             run += c[p];
         }
-        if (t == Group<P, NW, PPL>::NT - 1) cnt[NP] = run;
+        if (t == Group<P, NW, PPL, F>::NT - 1) cnt[NP] = run;
     }
     bsync<NW>();
 #pragma unroll
@@ -968,47 +986,62 @@ __device__ double run_trial(Group<P, NW, PPL> &G, unsigned char *lds, const Layo
             const uint32_t s = cnt[bkt[p]], e = cnt[bkt[p] + 1];
             uint32_t rank = 0;
             for (uint32_t i = s; i < e; ++i) rank += tmp[i] < key[p] ? 1u : 0u;
-            const uint32_t pos = s + rank;
-            SK[pos] = key[p];
-            if constexpr (!kCache) {
-                sy[pos] = od.y[j];
-                sw[pos] = od.w[j];
-            }
+            SK[s + rank] = key[p];
         }
     }
     bsync<NW>();
-    S x[PPL], wx[PPL];
-    R y[PPL], w[PPL];
     bool tie = false;
 #pragma unroll
     for (int p = 0; p < PPL; ++p) {
         const int j = t * PPL + p;
-        const bool ok = j < n;
-        const uint64_t k = ok ? SK[j] : ~0ull;
-        if constexpr (kCache) {
-            const int i = ok ? (int)(k & 0xffffu) : 0;  // original index of the sorted point
-            y[p] = ok ? cy[i] : R(0);
-            w[p] = ok ? cw[i] : R(0);
-        } else {
-            y[p] = ok ? sy[j] : R(0);
-            w[p] = ok ? sw[j] : R(0);
-        }
-        x[p] = ok ? P::x_of_key(k) : P::zero();
-        wx[p] = P::mulr(x[p], w[p]);
-        if (j + 1 < n) tie |= (SK[j + 1] >> 16) == (k >> 16);
+        if (j + 1 < n) tie |= (SK[j + 1] >> 16) == (SK[j] >> 16);
     }
     if constexpr (NW == 1) {
         G.ties = wave_ballot(tie) != 0;
     } else {
         G.ties = __syncthreads_or(tie) != 0;
     }
+    if ((SK[n - 1] >> 16) <= (SK[0] >> 16)) return true;
+    const int q = n / 4;
+    const double scale =
+        (double)(SK[3 * q - 1] >> 16) * 0x1p-48 - (double)(SK[q - 1] >> 16) * 0x1p-48;
+    G.vsmlsq = listing_vsmlsq(scale);
+    return false;
+}
+
+// The smoother and the score of one object on the sorted keys of fold_sort:
+// gathers the object's y, w in phase order (from the item's LDS object cache,
+// or from global memory through the key's index), runs Listing 1 or the
+// single-pass variant, returns P = 1 - chi2/chi0.
+template <class P, int NW, int PPL, int METHOD, bool PDM, bool CACHE_YW, int F>
+__device__ double score_sorted(Group<P, NW, PPL, F> &G, unsigned char *lds, const Layout &Y,
+                               const TrialLaunch &L, const typename P::R *y_src,
+                               const typename P::R *w_src, bool flat, double chi0, double &pdm) {
+    using R = typename P::R;
+    using S = typename P::S;
+    const int n = G.n, t = G.t, NP = Y.np;
+    const R *cy = (const R *)(lds + Y.obj + NP * 8);
+    const R *cw = (const R *)(lds + Y.obj + 2 * NP * 8);
+    const uint64_t *SK = (const uint64_t *)(lds + Y.sk);
+    S x[PPL], wx[PPL];
+    R y[PPL], w[PPL];
+#pragma unroll
+    for (int p = 0; p < PPL; ++p) {
+        const int j = t * PPL + p;
+        const bool ok = j < n;
+        const uint64_t k = ok ? SK[j] : ~0ull;
+        const int i = ok ? (int)(k & 0xffffu) : 0;  // original index of the sorted point
+        y[p] = ok ? (CACHE_YW ? cy : y_src)[i] : R(0);
+        w[p] = ok ? (CACHE_YW ? cw : w_src)[i] : R(0);
+        x[p] = ok ? P::x_of_key(k) : P::zero();
+        wx[p] = P::mulr(x[p], w[p]);
+    }
     if constexpr (PDM) {
         const int B = L.pdm_bins > 0 ? L.pdm_bins : min(32, max(4, n / 5));
         pdm = pdm_score<P, NW, PPL>(G, B, w, y, chi0);
     }
-
     // ---- Listing 1: constant fit when the phases do not spread
-    if ((SK[n - 1] >> 16) <= (SK[0] >> 16)) {
+    if (flat) {
         double a = 0.0, sw_ = 0.0;
 #pragma unroll
         for (int p = 0; p < PPL; ++p) {
@@ -1022,21 +1055,27 @@ __device__ double run_trial(Group<P, NW, PPL> &G, unsigned char *lds, const Layo
         for (int p = 0; p < PPL; ++p) smo[p] = m;
         return 1.0 - chi2_of<P, NW, PPL>(G, w, y, smo) * G.inv_chi0;
     }
-    {
-        const int q = n / 4;
-        const double scale = (double)(SK[3 * q - 1] >> 16) * 0x1p-48 -
-                             (double)(SK[q - 1] >> 16) * 0x1p-48;
-        G.vsmlsq = listing_vsmlsq(scale);
-    }
     const double chi2 = (METHOD == 0) ? supersmoother<P, NW, PPL>(G, L, x, w, wx, y)
                                       : single_pass<P, NW, PPL, METHOD == 2>(G, L, x, w, wx, y);
     return 1.0 - chi2 * G.inv_chi0;
 }
 
+// Objects longer than the object cache (groups of more than 1,024 points)
+// read y, w from global memory through the sorted index.
+template <class P, int NW, int PPL, int METHOD, bool PDM, int F>
+__device__ double run_trial(Group<P, NW, PPL, F> &G, unsigned char *lds, const Layout &Y,
+                            const TrialLaunch &L, const ObjData<P> &od, double f, double chi0,
+                            double &pdm) {
+    constexpr bool kCache = caches_object(kWave * NW * PPL);
+    const bool flat = fold_sort<P, NW, PPL, kCache>(G, lds, Y, od.tt, f);
+    return score_sorted<P, NW, PPL, METHOD, PDM, kCache>(G, lds, Y, L, od.y, od.w, flat, chi0,
+                                                         pdm);
+}
+
 // One work item: an object and a run of consecutive trial frequencies (a tile
 // of the full grid, or one refine range).
-template <class P, int NW, int PPL, int METHOD, bool PDM>
-__device__ void run_item(Group<P, NW, PPL> &G, unsigned char *lds, const Layout &Y,
+template <class P, int NW, int PPL, int METHOD, bool PDM, int F>
+__device__ void run_item(Group<P, NW, PPL, F> &G, unsigned char *lds, const Layout &Y,
                          const TrialLaunch &L, int64_t item) {
     using R = typename P::R;
     const int64_t ci = item / L.n_tiles;
@@ -1109,6 +1148,94 @@ __device__ void run_item(Group<P, NW, PPL> &G, unsigned char *lds, const Layout 
     }
 }
 
+// Shared time sampling (Sec. 2.2: objects observed at the same times fold
+// and sort alike): a work item is a batch of up to L.shared_batch objects of
+// the class and a frequency tile.  Every trial frequency is folded and
+// sorted once; each object of the batch then gathers its own y, w through
+// the sorted index and runs the smoother.  The item's running maxima are
+// kept in LDS (written by thread 0 only).
+template <class P, int NW, int PPL, int METHOD, int F>
+__device__ void run_item_shared(Group<P, NW, PPL, F> &G, unsigned char *lds, const Layout &Y,
+                                const TrialLaunch &L, int64_t item) {
+    using R = typename P::R;
+    const int64_t bi = item / L.n_tiles;
+    const int32_t tile = (int32_t)(item - bi * L.n_tiles);
+    const int count = *L.count;
+    const int m0 = (int)(bi * L.shared_batch);
+    const int m1 = min(m0 + L.shared_batch, count);
+    const int64_t k0 = (int64_t)tile * L.tile_f;
+    const int64_t k1 = (k0 + L.tile_f < L.n_freq) ? k0 + L.tile_f : L.n_freq;
+    double *bp = (double *)(lds + Y.best);
+    int32_t *bk = (int32_t *)(lds + Y.best + kMaxSharedBatch * 8);
+    // a batch without a usable object does no trial (its light curves may be
+    // too short or too long for this group)
+    bool any_ok = false;
+    for (int m = m0; m < m1; ++m) any_ok |= L.cat.status[L.objs[m]] == 0;
+    if (!any_ok) {
+        for (int m = m0; m < m1; ++m) {
+            const int64_t row = (int64_t)L.objs[m] * L.n_freq;
+            for (int64_t k = k0 + G.t; k < k1; k += kWave * NW) {
+                if (L.pgram64) L.pgram64[row + k] = __builtin_nan("");
+                if (L.pgram32) L.pgram32[row + k] = __builtin_nanf("");
+            }
+            if (G.t == 0 && L.part_p) {
+                const int64_t part = (int64_t)L.objs[m] * L.n_tiles + tile;
+                L.part_p[part] = __builtin_nan("");
+                L.part_k[part] = -1;
+            }
+        }
+        return;
+    }
+    G.n = L.shared_n;
+    G.inv_n = 1.0 / (double)G.n;
+    constexpr bool kCache = caches_object(kWave * NW * PPL);
+    if constexpr (kCache) {
+        double *ct = (double *)(lds + Y.obj);
+        for (int i = G.t; i < G.n; i += kWave * NW) ct[i] = L.shared_tt[i];
+    }
+    if (G.t == 0)
+        for (int m = 0; m < m1 - m0; ++m) {
+            bp[m] = 0.0;
+            bk[m] = -1;
+        }
+    bsync<NW>();
+    for (int64_t k = k0; k < k1; ++k) {
+        const double f = grid_freq(L.fmin, L.df, k);
+        const bool flat = fold_sort<P, NW, PPL, kCache>(G, lds, Y, L.shared_tt, f);
+        for (int m = m0; m < m1; ++m) {
+            const int obj = L.objs[m];
+            const int64_t row = (int64_t)obj * L.n_freq;
+            double Pk = __builtin_nan("");
+            if (L.cat.status[obj] == 0) {
+                const int64_t base = L.cat.offsets[obj];
+                const double chi0 = L.cat.chi0[obj];
+                G.inv_chi0 = 1.0 / chi0;
+                const R *yo = (P::kIsF64 ? (const R *)L.cat.yc : (const R *)L.cat.yc32) + base;
+                const R *wo = (P::kIsF64 ? (const R *)L.cat.w : (const R *)L.cat.w32) + base;
+                double pdm = 0.0;
+                Pk = score_sorted<P, NW, PPL, METHOD, false, false>(G, lds, Y, L, yo, wo, flat,
+                                                                    chi0, pdm);
+            }
+            if (G.t == 0) {
+                if (L.pgram64) L.pgram64[row + k] = Pk;
+                if (L.pgram32) L.pgram32[row + k] = (float)Pk;
+                const int i = m - m0;
+                if (!__builtin_isnan(Pk) && (bk[i] < 0 || Pk > bp[i])) {
+                    bp[i] = Pk;
+                    bk[i] = (int32_t)k;
+                }
+            }
+        }
+    }
+    if (G.t == 0 && L.part_p)
+        for (int m = m0; m < m1; ++m) {
+            const int64_t part = (int64_t)L.objs[m] * L.n_tiles + tile;
+            const int i = m - m0;
+            L.part_p[part] = bk[i] < 0 ? __builtin_nan("") : bp[i];
+            L.part_k[part] = bk[i];
+        }
+}
+
 // Minimum wavefronts per SIMD the compiler must fit each kernel into (its
 // register budget: 512 / waves registers per lane).  Measured on MI355X per
 // precision, shape and method: a budget that forces a few spills but raises
@@ -1134,18 +1261,15 @@ constexpr int waves_per_simd() {
 // Persistent: every workgroup takes items from the class queue until all
 // count * n_tiles items are handed out (each workgroup exits after at most
 // one failed take).
-template <class P, int NW, int PPL, int METHOD, bool PDM>
+template <class P, int NW, int PPL, int METHOD, bool PDM, bool SHARED = false>
 __global__ __launch_bounds__(kWave *NW,
                              (PDM ? 1 : waves_per_simd<P::kIsF64, NW, PPL, METHOD>()))
 void trial_kernel(TrialLaunch L) {
     using S = typename P::S;
     extern __shared__ __align__(16) unsigned char lds[];
     const Layout Y(NW, PPL, L.ext, METHOD);
-    Group<P, NW, PPL> G;
-    G.A0 = (S *)lds;
-    G.A1 = (S *)(lds + Y.arr);
-    G.A2 = (S *)(lds + 2 * Y.arr);
-    G.A3 = (S *)(lds + 3 * Y.arr);  // used only where the layout has a fourth array
+    Group<P, NW, PPL, prefix_arrays(METHOD, NW, PPL)> G;
+    G.Q = (S *)lds;
     G.SK = (const uint64_t *)(lds + Y.sk);
     G.xs = (S *)(lds + Y.xch);
     G.xd = (double *)(lds + Y.xch);
@@ -1158,7 +1282,10 @@ void trial_kernel(TrialLaunch L) {
     G.inv_n = 0.0;
     G.inv_chi0 = 0.0;
     G.n = 0;
-    const unsigned long long total = (unsigned long long)(*L.count) * (unsigned long long)L.n_tiles;
+    const unsigned long long units =
+        SHARED ? (unsigned long long)((*L.count + L.shared_batch - 1) / L.shared_batch)
+               : (unsigned long long)(*L.count);
+    const unsigned long long total = units * (unsigned long long)L.n_tiles;
     unsigned long long *take = (unsigned long long *)(lds + Y.qslot);
     for (;;) {
         bsync<NW>();
@@ -1166,14 +1293,17 @@ void trial_kernel(TrialLaunch L) {
         bsync<NW>();
         const unsigned long long item = *take;
         if (item >= total) break;
-        run_item<P, NW, PPL, METHOD, PDM>(G, lds, Y, L, (int64_t)item);
+        if constexpr (SHARED)
+            run_item_shared<P, NW, PPL, METHOD>(G, lds, Y, L, (int64_t)item);
+        else
+            run_item<P, NW, PPL, METHOD, PDM>(G, lds, Y, L, (int64_t)item);
     }
 }
 
-template <class P, int NW, int PPL, int METHOD, bool PDM>
+template <class P, int NW, int PPL, int METHOD, bool PDM, bool SHARED = false>
 hipError_t launch_variant(const TrialLaunch &L, int64_t max_items, int n_cu, hipStream_t s) {
     const Layout Y(NW, PPL, L.ext, METHOD);
-    const void *fn = (const void *)trial_kernel<P, NW, PPL, METHOD, PDM>;
+    const void *fn = (const void *)trial_kernel<P, NW, PPL, METHOD, PDM, SHARED>;
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, Y.bytes);
     if (e != hipSuccess) return e;
     int per_cu = 0;
@@ -1183,7 +1313,7 @@ hipError_t launch_variant(const TrialLaunch &L, int64_t max_items, int n_cu, hip
     int64_t grid = (int64_t)per_cu * n_cu;
     if (grid > max_items) grid = max_items;
     if (grid < 1) grid = 1;
-    hipLaunchKernelGGL((trial_kernel<P, NW, PPL, METHOD, PDM>), dim3((unsigned)grid),
+    hipLaunchKernelGGL((trial_kernel<P, NW, PPL, METHOD, PDM, SHARED>), dim3((unsigned)grid),
                        dim3(kWave * NW), (size_t)Y.bytes, s, L);
     return hipGetLastError();
 }
@@ -1192,6 +1322,7 @@ hipError_t launch_variant(const TrialLaunch &L, int64_t max_items, int n_cu, hip
 // kernels keep their register allocation.
 template <class P, int NW, int PPL, int METHOD>
 hipError_t launch_one(const TrialLaunch &L, int64_t max_items, int n_cu, hipStream_t s) {
+    if (L.shared_batch > 0) return launch_variant<P, NW, PPL, METHOD, false, true>(L, max_items, n_cu, s);
     return (L.pdm64 || L.pdm32) ? launch_variant<P, NW, PPL, METHOD, true>(L, max_items, n_cu, s)
                                 : launch_variant<P, NW, PPL, METHOD, false>(L, max_items, n_cu, s);
 }

@@ -2,8 +2,8 @@
 
 Labels are the bin of the full-grid Super Smoother best frequency computed by
 the library itself (`ss_best_period`); training runs the library's own
-encoder gradient and Adam kernels (`ss_enc_train_grad`, `ss_adam_step`) on
-device-resident mini-batches.  Evaluation compares the search-and-refine
+gradient and Adam kernels through one `ss_train_step` per device-resident
+mini-batch on a model object (`ss_model_*`).  Evaluation compares the search-and-refine
 result (`ss_learned_best_period`) with the full-grid result on the same
 objects: agreement is the fraction of objects whose refined best index equals
 the full-grid best index, and the speed-up is the ratio of the two calls'
@@ -18,7 +18,7 @@ import time
 import numpy as np
 import torch
 
-from . import (DeviceCatalog, ENC_BINS, ENC_PARAMS, SS_FP64, SS_METHOD_SS, Params, adam_step,
+from . import (DeviceCatalog, ENC_BINS, ENC_PARAMS, SS_FP64, SS_METHOD_SS, Model, Params,
                bin_table)
 
 
@@ -65,34 +65,31 @@ def labels_from_best(best_idx: np.ndarray, grid) -> np.ndarray:
 
 
 def train(ctx, dc: DeviceCatalog, labels: np.ndarray, grid, epochs: int = 10, batch: int = 512,
-          lr: float = 2e-3, seed: int = 0, params: np.ndarray | None = None, log=None):
+          lr: float = 2e-3, seed: int = 0, params: np.ndarray | None = None, log=None,
+          model: Model | None = None):
     """Adam on mean cross-entropy over fixed contiguous batches in a shuffled
-    order each epoch.  Returns (params tensor, per-epoch mean losses)."""
+    order each epoch, one ss_train_step per batch on a model object (a new one
+    from init_params(seed) or `params`, or `model` to continue training).
+    Returns (current parameters as a tensor, per-epoch mean losses, model)."""
     dev = dc.offsets.device
-    p = torch.tensor(init_params(seed) if params is None else params, dtype=torch.float32,
-                     device=dev)
-    m = torch.zeros_like(p)
-    v = torch.zeros_like(p)
-    g = torch.empty_like(p)
+    if model is None:
+        model = Model.create(ctx, grid, init_params(seed) if params is None else params)
     loss = torch.empty(1, dtype=torch.float32, device=dev)
     lab = torch.tensor(labels, dtype=torch.int32, device=dev)
     n = dc.n_obj
     starts = np.arange(0, n, batch)
     rng = np.random.default_rng(seed)
-    step = 0
     history = []
     for ep in range(epochs):
         tot = torch.zeros((), dtype=torch.float64, device=dev)
         for lo in rng.permutation(starts):
             hi = min(n, lo + batch)
-            ctx.enc_train_grad(view(dc, lo, hi), grid, p, lab[lo:hi], grad=g, loss=loss)
-            step += 1
-            adam_step(p, g, m, v, step, lr)
+            model.train_step(ctx, view(dc, lo, hi), lab[lo:hi], lr, loss=loss)
             tot += loss[0].double() * (hi - lo)
         history.append(float(tot.item()) / n)
         if log:
             log(f"epoch {ep + 1}/{epochs}: loss {history[-1]:.4f}")
-    return p, history
+    return model.params(), history, model
 
 
 def topk_recall(ctx, dc: DeviceCatalog, grid, params, labels: np.ndarray, top_k: int = 16,
@@ -160,7 +157,7 @@ POLICY = {"gamma": 1.0, "top_k": 16, "margin": 0, "full_below": 80}
 
 def main(argv=None) -> int:
     """Labels the training set with the full-grid search, trains the encoder
-    and writes its parameters (float32 .npy)."""
+    and writes its parameters (float32 .npy) and the model file (.ssm)."""
     import argparse
     import os
 
@@ -189,8 +186,8 @@ def main(argv=None) -> int:
             np.save(args.labels_cache, lab)
     n_val = max(1, args.n_train // 20)
     n_tr = args.n_train - n_val
-    p, hist = train(ctx, view(dc, 0, n_tr), lab[:n_tr], grid, epochs=args.epochs,
-                    batch=args.batch, lr=args.lr, log=lambda s: print(s, flush=True))
+    p, hist, model = train(ctx, view(dc, 0, n_tr), lab[:n_tr], grid, epochs=args.epochs,
+                           batch=args.batch, lr=args.lr, log=lambda s: print(s, flush=True))
     p0 = torch.tensor(init_params(0), dtype=torch.float32, device=dc.offsets.device)
     r0 = topk_recall(ctx, view(dc, n_tr, args.n_train), grid, p0, lab[n_tr:])
     r1 = topk_recall(ctx, view(dc, n_tr, args.n_train), grid, p, lab[n_tr:])
@@ -198,6 +195,8 @@ def main(argv=None) -> int:
           f"trained {r1:.4f}", flush=True)
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
     np.save(args.out, p.cpu().numpy())
+    model.save(os.path.splitext(args.out)[0] + ".ssm")  # parameters + Adam state + grid
+    model.close()
     ctx.close()
     return 0
 

@@ -105,3 +105,8 @@ def test_bench_source_hash_ignores_comments_but_not_code(tmp_path):
     assert bench._src_hash(str(tmp_path)) == h0
     (tmp_path / "trial_impl.hpp").write_text(src.replace("np <= 1024", "np <= 512", 1))
     assert bench._src_hash(str(tmp_path)) != h0
+
+
+def test_tuner_source_key_ignores_comments():
+    k = tune.source_key()
+    assert len(k) == 16 and k == tune.source_key()

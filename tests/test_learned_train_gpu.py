@@ -29,7 +29,7 @@ def test_training_and_proposal_gain():
     assert (st == 0).all()
     lab = learn.labels_from_best(bi, grid)
     n_tr = 2500
-    p, hist = learn.train(ctx, learn.view(dc, 0, n_tr), lab[:n_tr], grid, epochs=15, batch=256,
+    p, hist, _ = learn.train(ctx, learn.view(dc, 0, n_tr), lab[:n_tr], grid, epochs=15, batch=256,
                           lr=2e-3)
     print("loss per epoch", [round(h, 4) for h in hist])
     assert hist[-1] < hist[0] - 0.05

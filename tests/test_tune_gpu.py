@@ -1,6 +1,6 @@
-"""The shape autotuner on the GPU: it times the shapes that hold each length
-range of a catalog, installs the fastest per range, caches the choice, and
-the search keeps its oracle parity under the tuned shapes."""
+"""The autotuner on the GPU: it times the shapes that hold each length range
+of a catalog and then the frequency tile, installs the fastest, caches the
+choices, and the search keeps its oracle parity under the tuned settings."""
 import json
 
 import numpy as np
@@ -19,18 +19,20 @@ def test_tuner_installs_valid_shapes_and_keeps_parity(tmp_path):
     grid = (0.1, 10.0, 1500)
     ctx = ssg.Context(0)
     cache = str(tmp_path / "tune.json")
-    chosen = tune.tune(ctx, cat.offsets, cat.t, cat.y, cat.e, grid, sample_objects=16,
-                       sample_freqs=256, cache_path=cache)
+    chosen, tile = tune.tune(ctx, cat.offsets, cat.t, cat.y, cat.e, grid, sample_objects=16,
+                             sample_freqs=256, cache_path=cache)
+    assert tile is not None and tile[0] in tune.TILES and tile[1] > 0
     lens = np.diff(cat.offsets)
     assert chosen
     for (lo, hi), (nw, ppl, rate) in chosen.items():
         assert (nw, ppl) in ssg.shapes() and 64 * nw * ppl >= hi and rate > 0
         assert ((lens > lo) & (lens <= hi)).any()
     with open(cache) as f:
-        assert len(json.load(f)) == len(chosen)
+        assert len(json.load(f)) == len(chosen) + 1  # the ranges and the tile
     # a second tuner call reuses the cache
-    again = tune.tune(ctx, cat.offsets, cat.t, cat.y, cat.e, grid, cache_path=cache)
+    again, tile2 = tune.tune(ctx, cat.offsets, cat.t, cat.y, cat.e, grid, cache_path=cache)
     assert {k: v[:2] for k, v in again.items()} == {k: v[:2] for k, v in chosen.items()}
+    assert tile2[0] == tile[0]
     dc = ssg.DeviceCatalog.from_numpy(cat.offsets, cat.t, cat.y, cat.e)
     bi, bp, bw, st = ctx.ss_best_period(oracle.SS, dc, grid)
     torch.cuda.synchronize()
