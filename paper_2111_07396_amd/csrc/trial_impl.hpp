@@ -31,15 +31,17 @@ namespace {
 // ------------------------------------------------------------------ layout
 // Prefix storage: slot u holds F consecutive values: the x-moment prefixes
 // (W, X, XX) in fields 0..2 during the geometry phase, then a prefix pair
-// (V, XV) in fields 0, 1 and, for double-buffered groups (F = 4), a second
-// pair in fields 2, 3.  A window end is then one address with constant
-// offsets (paired 16-byte loads) instead of one address per prefix array.
+// (V, XV) in fields 0, 1.  Double-buffered groups (F = 5) hold the prefix
+// pair of y in fields 3, 4 beside the x-moments (phases A1 and A2 share one
+// pass), and alternate their later pairs between fields (0, 1) and (2, 3).
+// A window end is then one address with constant offsets (paired loads)
+// instead of one address per prefix array.
 // After every PPL slots come pad_q values: the 64 lanes read at a common
 // offset from their own PPL consecutive slots, and the pad makes the lane
 // stride an odd number of 8-byte words (F = 3) or of 16-byte words (F = 4),
 // so that the lanes of one LDS cycle fall in distinct banks.
 constexpr __host__ __device__ int pad_q(int f, int ppl) {
-    return f == 4 ? 2 : (ppl % 2 == 0 ? 1 : 0);
+    return f == 4 ? 2 : ((f * ppl) % 2 == 0 ? 1 : 0);
 }
 template <int F, int PPL>
 __device__ __forceinline__ int qaddr(int u) {
@@ -63,7 +65,7 @@ constexpr __host__ __device__ bool double_buffered(int method, int nw, int ppl) 
     return method == 0 && nw > 1 && caches_object(kWave * nw * ppl);
 }
 constexpr __host__ __device__ int prefix_arrays(int method, int nw, int ppl) {
-    return double_buffered(method, nw, ppl) ? 4 : 3;
+    return double_buffered(method, nw, ppl) ? 5 : 3;
 }
 
 // LDS layout of one trial group; identical on host and device.  The prefix
@@ -382,21 +384,25 @@ __device__ __forceinline__ typename P::Geo geometry(const Group<P, NW, PPL, F> &
                   xj, G.vsmlsq, h);
 }
 
-template <class P, int NW, int PPL, int F>
+// Fit of the prefix pair in fields (OFF, OFF + 1) at point j, half-width b.
+template <class P, int NW, int PPL, int F, int OFF = 0>
 __device__ __forceinline__ typename P::R window_fit(const Group<P, NW, PPL, F> &G,
                                                     const typename P::Geo &g, int j, int b) {
-    const int hi = G.at(j + b + 1), lo = G.at(j - b);
+    const int hi = G.at(j + b + 1) + OFF, lo = G.at(j - b) + OFF;
     const typename P::S *Q = G.Q;
     return P::eval(g, P::sub(Q[hi], Q[lo]), P::sub(Q[hi + 1], Q[lo + 1]));
 }
 
 // ------------------------------------------------------------------ rare paths
 // Kept out of line; they work on LDS only, so no register arrays cross the
-// call.
+// call.  One copy per kernel (the TAG template argument): a function shared by
+// kernels of different register budgets is compiled for the tightest of
+// them, and the callers' register allocation then depends on the other
+// kernels in the file.
 
 // out[j] (j in [j0, j1)) = weighted mean of s over the run of equal phase
 // holding j, or s[j] when the phase of j is unique.
-template <class R>
+template <class R, int TAG>
 __device__ __noinline__ void tie_means(const R *s, const R *w, R *out, const uint64_t *SK, int n,
                                        int j0, int j1) {
     for (int j = j0; j < j1; ++j) {
@@ -419,7 +425,7 @@ __device__ __noinline__ void tie_means(const R *s, const R *w, R *out, const uin
 
 // out[j] = r[j] where r[j] >= 0, else the nearest earlier non-negative r
 // (0 if none): the CV residual of a point with 1 - w h <= 0.
-template <class R>
+template <class R, int TAG>
 __device__ __noinline__ void fallback_fill(const R *r, R *out, int j0, int j1) {
     for (int j = j0; j < j1; ++j) {
         if (r[j] >= R(0)) {
@@ -450,7 +456,8 @@ __device__ void tie_average(const Group<P, NW, PPL, F> &G, const typename P::R (
         }
     }
     bsync<NW>();
-    tie_means<R>(S1, S2, S3, G.SK, G.n, min(G.t * PPL, G.n), min(G.t * PPL + PPL, G.n));
+    tie_means<R, (NW * 8 + PPL) * 8 + F>(S1, S2, S3, G.SK, G.n, min(G.t * PPL, G.n),
+                                         min(G.t * PPL + PPL, G.n));
     bsync<NW>();
 #pragma unroll
     for (int p = 0; p < PPL; ++p) {
@@ -483,7 +490,8 @@ __device__ void cv_fallback(const Group<P, NW, PPL, F> &G, bool any, typename P:
         if (j < G.n) S1[j] = r[p];
     }
     bsync<NW>();
-    fallback_fill<R>(S1, S2, min(G.t * PPL, G.n), min(G.t * PPL + PPL, G.n));
+    fallback_fill<R, (NW * 8 + PPL) * 8 + F>(S1, S2, min(G.t * PPL, G.n),
+                                             min(G.t * PPL + PPL, G.n));
     bsync<NW>();
 #pragma unroll
     for (int p = 0; p < PPL; ++p) {
@@ -590,11 +598,53 @@ __device__ __forceinline__ void prefix_x(const Group<P, NW, PPL, F> &G,
     }
 }
 
+// Phases A1 and A2 in one pass (five prefix fields per slot): the x-moment
+// prefixes W, X, XX in fields 0..2 and the prefix pair of y in fields 3, 4,
+// extended by e (two group scans of 3 and 2 quantities: one scan of all
+// five holds more registers at once).
+template <class P, int NW, int PPL, int F>
+__device__ __forceinline__ void prefix_xy(const Group<P, NW, PPL, F> &G,
+                                          const typename P::S (&x)[PPL],
+                                          const typename P::R (&w)[PPL],
+                                          const typename P::S (&wx)[PPL],
+                                          const typename P::R (&y)[PPL], int e) {
+    static_assert(F >= 5, "five prefix fields");
+    using S = typename P::S;
+    constexpr bool kFused = fused_extension<P::kIsF64, NW, PPL>();
+    bsync<NW>();
+    {
+        S q[3][PPL];
+#pragma unroll
+        for (int p = 0; p < PPL; ++p) {
+            q[0][p] = P::from(w[p]);
+            q[1][p] = wx[p];
+            q[2][p] = P::mul(wx[p], x[p]);
+        }
+        S *const Pf[3] = {G.Q, G.Q + 1, G.Q + 2};
+        S T[3];
+        build_prefix<P, NW, PPL, 3, kFused>(G, Pf, q, T, e);
+        if constexpr (!kFused) extend3<P, NW, PPL>(G, G.Q, G.Q + 1, G.Q + 2, T, e);
+    }
+    {
+        S q[2][PPL];
+#pragma unroll
+        for (int p = 0; p < PPL; ++p) {
+            q[0][p] = P::prod(w[p], y[p]);
+            q[1][p] = P::mulr(wx[p], y[p]);
+        }
+        S *const Pf[2] = {G.Q + 3, G.Q + 4};
+        S T[2];
+        build_prefix<P, NW, PPL, 2, kFused>(G, Pf, q, T, e);
+        if constexpr (!kFused) extend2<P, NW, PPL>(G, G.Q + 3, G.Q + 4, T, e);
+    }
+}
+
 // ------------------------------------------------------------------ Listing 1
 template <class P, int NW, int PPL, int F>
 __device__ double supersmoother(const Group<P, NW, PPL, F> &G, const TrialLaunch &L,
                                 const typename P::S (&x)[PPL], const typename P::R (&w)[PPL],
-                                const typename P::S (&wx)[PPL], const typename P::R (&y)[PPL]) {
+                                const typename P::S (&wx)[PPL], const typename P::R (&y)[PPL],
+                                const typename P::R *ysrc) {
     using R = typename P::R;
     using Geo = typename P::Geo;
     const int n = G.n, t = G.t;
@@ -615,29 +665,60 @@ __device__ double supersmoother(const Group<P, NW, PPL, F> &G, const TrialLaunch
               b2 = halfwidth(n, L.span[2]);
     const R sp0 = (R)L.span[0], sp1 = (R)L.span[1], sp2 = (R)L.span[2];
 
-    // ---- phase A1: geometry of the three spans
-    Geo g0[PPL], g1[PPL], g2[PPL];
-    R h0[PPL], h1[PPL], h2[PPL];
-    prefix_x<P, NW, PPL>(G, x, w, wx, b2);
-#pragma unroll
-    for (int p = 0; p < PPL; ++p) {
-        const int j = min(t * PPL + p, n - 1);
-        g0[p] = geometry<P, NW, PPL>(G, j, b0, x[p], h0[p]);
-        g1[p] = geometry<P, NW, PPL>(G, j, b1, x[p], h1[p]);
-        g2[p] = geometry<P, NW, PPL>(G, j, b2, x[p], h2[p]);
-    }
-    // ---- phase A2: the cross-validated smooths of y and their |CV residuals|
+    Geo g0[PPL], g1[PPL];
     R s0[PPL], s1[PPL], s2[PPL], r0[PPL], r1[PPL], r2[PPL];
-    prefix_pair<P, NW, PPL>(G, w, wx, y, b2);
+    if constexpr (F >= 5) {
+        // ---- phases A1 + A2 in one pass, span by span: geometry, fit and
+        // |CV residual|; only the geometries used later stay live
+        prefix_xy<P, NW, PPL>(G, x, w, wx, y, b2);
 #pragma unroll
-    for (int p = 0; p < PPL; ++p) {
-        const int j = min(t * PPL + p, n - 1);
-        s0[p] = window_fit<P, NW, PPL>(G, g0[p], j, b0);
-        s1[p] = window_fit<P, NW, PPL>(G, g1[p], j, b1);
-        s2[p] = window_fit<P, NW, PPL>(G, g2[p], j, b2);
-        r0[p] = cv_resid<P>(y[p], s0[p], w[p], h0[p]);
-        r1[p] = cv_resid<P>(y[p], s1[p], w[p], h1[p]);
-        r2[p] = cv_resid<P>(y[p], s2[p], w[p], h2[p]);
+        for (int p = 0; p < PPL; ++p) {
+            const int j = min(t * PPL + p, n - 1);
+            R h;
+            const Geo g2 = geometry<P, NW, PPL>(G, j, b2, x[p], h);
+            s2[p] = window_fit<P, NW, PPL, F, 3>(G, g2, j, b2);
+            r2[p] = cv_resid<P>(y[p], s2[p], w[p], h);
+        }
+#pragma unroll
+        for (int p = 0; p < PPL; ++p) {
+            const int j = min(t * PPL + p, n - 1);
+            R h;
+            g1[p] = geometry<P, NW, PPL>(G, j, b1, x[p], h);
+            s1[p] = window_fit<P, NW, PPL, F, 3>(G, g1[p], j, b1);
+            r1[p] = cv_resid<P>(y[p], s1[p], w[p], h);
+        }
+#pragma unroll
+        for (int p = 0; p < PPL; ++p) {
+            const int j = min(t * PPL + p, n - 1);
+            R h;
+            g0[p] = geometry<P, NW, PPL>(G, j, b0, x[p], h);
+            s0[p] = window_fit<P, NW, PPL, F, 3>(G, g0[p], j, b0);
+            r0[p] = cv_resid<P>(y[p], s0[p], w[p], h);
+        }
+    } else {
+        // ---- phase A1: geometry of the three spans
+        Geo g2[PPL];
+        R h0[PPL], h1[PPL], h2[PPL];
+        prefix_x<P, NW, PPL>(G, x, w, wx, b2);
+#pragma unroll
+        for (int p = 0; p < PPL; ++p) {
+            const int j = min(t * PPL + p, n - 1);
+            g0[p] = geometry<P, NW, PPL>(G, j, b0, x[p], h0[p]);
+            g1[p] = geometry<P, NW, PPL>(G, j, b1, x[p], h1[p]);
+            g2[p] = geometry<P, NW, PPL>(G, j, b2, x[p], h2[p]);
+        }
+        // ---- phase A2: the cross-validated smooths of y and their |CV residuals|
+        prefix_pair<P, NW, PPL>(G, w, wx, y, b2);
+#pragma unroll
+        for (int p = 0; p < PPL; ++p) {
+            const int j = min(t * PPL + p, n - 1);
+            s0[p] = window_fit<P, NW, PPL>(G, g0[p], j, b0);
+            s1[p] = window_fit<P, NW, PPL>(G, g1[p], j, b1);
+            s2[p] = window_fit<P, NW, PPL>(G, g2[p], j, b2);
+            r0[p] = cv_resid<P>(y[p], s0[p], w[p], h0[p]);
+            r1[p] = cv_resid<P>(y[p], s1[p], w[p], h1[p]);
+            r2[p] = cv_resid<P>(y[p], s2[p], w[p], h2[p]);
+        }
     }
     // ---- phase B: fallbacks and ties of the primaries
     constexpr bool kDB = double_buffered(0, NW, PPL);
@@ -715,7 +796,19 @@ __device__ double supersmoother(const Group<P, NW, PPL, F> &G, const TrialLaunch
     // tweeter smooth of the blend
     R smo[PPL];
     smooth_with<P, NW, PPL, kB1>(G, b0, g0, w, wx, rt, eb, smo);
-    return chi2_of<P, NW, PPL>(G, w, y, smo);
+    if constexpr (F >= 5) {
+        // y again from its source (the object cache or global memory) through
+        // the sorted index, rather than held in registers through phase B
+        R yy[PPL];
+#pragma unroll
+        for (int p = 0; p < PPL; ++p) {
+            const int j = t * PPL + p;
+            yy[p] = j < n ? ysrc[(int)(G.SK[j] & 0xffffu)] : R(0);
+        }
+        return chi2_of<P, NW, PPL>(G, w, yy, smo);
+    } else {
+        return chi2_of<P, NW, PPL>(G, w, y, smo);
+    }
 }
 
 // ------------------------------------------------------------------ Sec. 3
@@ -1055,7 +1148,8 @@ __device__ double score_sorted(Group<P, NW, PPL, F> &G, unsigned char *lds, cons
         for (int p = 0; p < PPL; ++p) smo[p] = m;
         return 1.0 - chi2_of<P, NW, PPL>(G, w, y, smo) * G.inv_chi0;
     }
-    const double chi2 = (METHOD == 0) ? supersmoother<P, NW, PPL>(G, L, x, w, wx, y)
+    const double chi2 = (METHOD == 0) ? supersmoother<P, NW, PPL>(G, L, x, w, wx, y,
+                                                                  CACHE_YW ? cy : y_src)
                                       : single_pass<P, NW, PPL, METHOD == 2>(G, L, x, w, wx, y);
     return 1.0 - chi2 * G.inv_chi0;
 }
@@ -1250,7 +1344,7 @@ constexpr int waves_per_simd() {
     if (NW == 1 && PPL == 3) return (F64 && ss) ? 2 : 1;
     if (NW == 1 && PPL == 4) return ss ? 1 : 2;
     if (NW == 2 && PPL == 1) return F64 ? 4 : (ss ? 3 : 1);
-    if (NW == 2 && PPL == 2) return ss ? (F64 ? 2 : 1) : 3;
+    if (NW == 2 && PPL == 2) return ss ? (F64 ? 3 : 1) : 3;
     if (NW == 4 && PPL == 1) return F64 ? 4 : (ss ? 3 : 1);
     if (NW == 2 && PPL == 3) return 1;  // FP64 SS held to 2 spilled to scratch and miscomputed
     if (NW == 4 && PPL == 2) return ss ? (F64 ? 2 : 1) : 3;
