@@ -228,6 +228,26 @@ int ss_periodogram_batched(ss_ctx *ctx, int32_t method, const ss_catalog *cat,
                            int64_t chunk_objs, ss_pgram_sink sink, void *user,
                            int32_t *obj_status, void *stream);
 
+/* Allocation-free best period, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, hosts that
+ * forbid allocation): ss_best_period computed in a fixed device region of
+ * SS_NOALLOC_BYTES that the library holds on every device it runs on until
+ * the process ends, instead of the context's growing workspace.  The call
+ * makes no hipMalloc or hipFree; the caller still passes the outputs.
+ * Needed: 32 bytes per point, 72 per object and 12 per object and frequency
+ * tile (tiles as chosen by ss_ctx_set_tile or automatically), each part
+ * rounded up to 256 bytes; a catalog that needs more than SS_NOALLOC_BYTES
+ * gets SS_ERR_UNSUPPORTED before any work is queued.  The size classes of a
+ * catalog run one after another on `stream` (not forked).  Every call on a
+ * device shares that device's region and leaves its contents behind: calls
+ * that overlap in time on one device (other streams, other threads, other
+ * contexts) race and give wrong results. */
+#define SS_NOALLOC_BYTES (64ll << 20)
+int ss_best_period_noalloc(ss_ctx *ctx, int32_t method, const ss_catalog *cat,
+                           const ss_grid *grid, const ss_params *params, int64_t *best_idx,
+                           double *best_period, double *best_power, int32_t *obj_status,
+                           void *stream);
+
 /* Trial-group shapes (autotuning).  One trial runs on a workgroup of `nw`
  * wavefronts whose threads hold `ppl` consecutive phase-sorted points each,
  * so a shape holds light curves of up to 64*nw*ppl points.  ss_num_shapes /

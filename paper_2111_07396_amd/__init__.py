@@ -35,7 +35,7 @@ EXPORTED = ("ss_params_default", "ss_ctx_create", "ss_ctx_destroy", "ss_periodog
             "ss_model_save", "ss_model_load", "ss_model_file_write", "ss_model_file_read",
             "ss_train_step", "ss_best_period_learned", "ss_model_copy_params",
             "ss_shared_periodogram", "ss_shared_best_period", "ss_plan_batches",
-            "ss_periodogram_batched")
+            "ss_periodogram_batched", "ss_best_period_noalloc")
 ENC_PARAMS = 145536
 ENC_BINS = 1024
 
@@ -115,6 +115,8 @@ def load_library(path: str = LIB_PATH):
     lib.ss_best_period.argtypes = [vp, i32, ctypes.POINTER(_Catalog), ctypes.POINTER(_Grid),
                                    ctypes.POINTER(_Params), vp, vp, vp, vp, vp]
     lib.ss_best_period.restype = ctypes.c_int
+    lib.ss_best_period_noalloc.argtypes = lib.ss_best_period.argtypes
+    lib.ss_best_period_noalloc.restype = ctypes.c_int
     lib.ss_num_shapes.argtypes = []
     lib.ss_num_shapes.restype = ctypes.c_int
     lib.ss_shape_info.argtypes = [ctypes.c_int, ctypes.POINTER(i32), ctypes.POINTER(i32)]
@@ -502,6 +504,19 @@ class Context:
         _check(_lib.ss_shared_best_period(self._h, int(method), ctypes.byref(c), ctypes.byref(g),
                                           ctypes.byref(p), _ptr(bi), _ptr(bp), _ptr(bw), _ptr(st),
                                           _stream_ptr(stream)))
+        return bi, bp, bw, st
+
+    def ss_best_period_noalloc(self, method, cat, grid, params=None, out=None, stream=None):
+        """ss_best_period in the library's fixed device region (no allocation
+        by the library; the outputs are allocated here unless `out` is given)."""
+        params = params or Params()
+        bi, bp, bw, st = self._best_out(cat.n_obj, cat.offsets.device, out)
+        g = _Grid(float(grid[0]), float(grid[1]), int(grid[2]))
+        c = cat._c()
+        p = params._c()
+        _check(_lib.ss_best_period_noalloc(self._h, int(method), ctypes.byref(c),
+                                           ctypes.byref(g), ctypes.byref(p), _ptr(bi), _ptr(bp),
+                                           _ptr(bw), _ptr(st), _stream_ptr(stream)))
         return bi, bp, bw, st
 
     def _best_out(self, n_obj, dev, out):

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <fstream>
+#include <mutex>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -106,6 +107,7 @@ struct Work {
 
 struct ss_ctx {
     int device = 0;
+    void *noalloc = nullptr;       // this device's copy of the fixed region
     Work cur;                      // workspace of the call in progress
     const Work *fixed = nullptr;   // when set: use it, never allocate
     DevBuf tt, w, yc, w32, yc32, chi0, sw, objs, counts, queues, part_p, part_k;
@@ -138,6 +140,21 @@ struct ss_model {
     float beta1 = 0.9f, beta2 = 0.999f, eps = 1e-8f;
     DevBuf params, m, v, grad;
 };
+
+// ---- the fixed region of the allocation-free entry point
+// Device memory that ss_best_period_noalloc uses in place of the context's
+// growing workspace.  Every device the library runs on holds its own copy
+// until the process ends; host code never uses the array's name as an
+// address, only the per-device address resolved by hipGetSymbolAddress.
+constexpr size_t kNoAllocBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+static_assert(kNoAllocBytes == (size_t)SS_NOALLOC_BYTES, "header and library agree");
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
 
 #define SS_HIP_TRY(expr, what)                                                               \
     do {                                                                                     \
@@ -650,6 +667,26 @@ int ss_ctx_create(int device, ss_ctx **out) {
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
         ncu > 0)
         c->n_cu = ncu;
+    // the fixed region's address on this device, resolved once per device
+    // with that device current
+    if (device < kMaxDevices) {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        if (!g_scratch_ptr[device]) {
+            int prev = 0;
+            hipError_t ge = hipGetDevice(&prev);
+            if (ge == hipSuccess) ge = hipSetDevice(device);
+            void *ptr = nullptr;
+            if (ge == hipSuccess) ge = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+            (void)hipSetDevice(prev);
+            if (ge != hipSuccess || !ptr) {
+                delete c;
+                return fail(SS_ERR_HIP, std::string("hipGetSymbolAddress: ") +
+                                            hipGetErrorString(ge));
+            }
+            g_scratch_ptr[device] = ptr;
+        }
+        c->noalloc = g_scratch_ptr[device];
+    }
     *out = c;
     return SS_OK;
 }
@@ -845,6 +882,52 @@ int ss_periodogram_batched(ss_ctx *ctx, int32_t method, const ss_catalog *cat,
         sink(user, lo, hi, chunk, obj_status + lo);
     }
     return SS_OK;
+}
+
+int ss_best_period_noalloc(ss_ctx *ctx, int32_t method, const ss_catalog *cat,
+                           const ss_grid *grid, const ss_params *params, int64_t *best_idx,
+                           double *best_period, double *best_power, int32_t *obj_status,
+                           void *stream) {
+    int rc = check_common(ctx, cat, grid, params);
+    if (rc != SS_OK) return rc;
+    if (method != SS_METHOD_SS && method != SS_METHOD_SSSP && method != SS_METHOD_SSSP_GV)
+        return fail(SS_ERR_INVALID_ARG, "method must be SS_METHOD_SS, _SSSP or _SSSP_GV");
+    if (cat->n_obj > 0 && (!best_idx || !best_period || !best_power || !obj_status))
+        return fail(SS_ERR_INVALID_ARG, "null output pointer");
+    if (!ctx->noalloc) return fail(SS_ERR_UNSUPPORTED, "no fixed region on this device");
+    const int64_t n_obj = cat->n_obj, total = cat->n_points;
+    if (n_obj == 0) return SS_OK;
+    const int32_t tile = tile_for(ctx, n_obj, grid->n_freq);
+    const int64_t n_tiles = (grid->n_freq + tile - 1) / tile;
+    // carve the region as the context's workspace would be laid out
+    uint64_t off = 0;
+    auto take = [&](uint64_t bytes) {
+        const uint64_t at = off;
+        off += (bytes + 255) / 256 * 256;
+        return (unsigned char *)ctx->noalloc + at;
+    };
+    Work W;
+    W.tt = (double *)take((uint64_t)total * 8);
+    W.w = (double *)take((uint64_t)total * 8);
+    W.yc = (double *)take((uint64_t)total * 8);
+    W.w32 = (float *)take((uint64_t)total * 4);
+    W.yc32 = (float *)take((uint64_t)total * 4);
+    W.chi0 = (double *)take((uint64_t)n_obj * 8);
+    W.sw = (double *)take((uint64_t)n_obj * 8);
+    W.objs = (int32_t *)take((uint64_t)n_obj * kNumShapes * 4);
+    W.counts = (int32_t *)take((uint64_t)kNumShapes * 4);
+    W.queues = (unsigned long long *)take((uint64_t)kNumShapes * 8);
+    W.part_p = (double *)take((uint64_t)n_obj * n_tiles * 8);
+    W.part_k = (int32_t *)take((uint64_t)n_obj * n_tiles * 4);
+    if (off > kNoAllocBytes)
+        return fail(SS_ERR_UNSUPPORTED,
+                    "catalog needs " + std::to_string(off) + " bytes of working memory; the "
+                    "allocation-free entry point has " + std::to_string(kNoAllocBytes));
+    ctx->fixed = &W;
+    rc = run(ctx, method, cat, grid, params, nullptr, nullptr, true, obj_status,
+             (hipStream_t)stream, best_idx, best_period, best_power);
+    ctx->fixed = nullptr;
+    return rc;
 }
 
 int ss_num_shapes(void) { return kNumShapes; }
