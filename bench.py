@@ -190,6 +190,7 @@ def _extras(ctx, ssg, synth, args):
         ex["single_dense"][pn] = {names[m]: {"ms": r[m]["wall_ms"], "trials_per_s":
                                              r[m]["trials_per_s"]} for m in both}
     ex["method_accuracy"] = _method_accuracy(ctx, ssg, synth)
+    ex["shared_sampling"] = _shared_sampling(ctx, ssg, synth)
     ex.update(_proposal(ctx, ssg, synth, args))
     return ex
 
@@ -259,6 +260,109 @@ def _proposal(ctx, ssg, synth, args):
     return ex
 
 
+def _host_cpu():
+    """CPU model, logical CPUs and physical cores of this host (Linux)."""
+    model, phys = "unknown", set()
+    try:
+        cur = {}
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if ":" not in line:
+                    if cur:
+                        phys.add((cur.get("physical id"), cur.get("core id")))
+                    cur = {}
+                    continue
+                k, v = [x.strip() for x in line.split(":", 1)]
+                cur[k] = v
+                if k == "model name":
+                    model = v
+        if cur:
+            phys.add((cur.get("physical id"), cur.get("core id")))
+    except OSError:
+        pass
+    return model, os.cpu_count(), len(phys)
+
+
+def _cpu_baseline(cat, grid, n_sample):
+    """The FP64 C oracle on the host cores: the first n_sample objects of the
+    benchmark catalog on the whole grid, both methods (OpenMP over trials)."""
+    import numpy as np
+    import oracle
+    sub = cat.subset(np.arange(min(n_sample, cat.n_obj)))
+    n_freq = int(grid[2])
+    c0 = time.perf_counter()
+    for m in (oracle.SS, oracle.SSSP):
+        oracle.periodogram(m, sub.offsets, sub.t, sub.y, sub.e, *grid)
+    c1 = time.perf_counter()
+    model, logical, physical = _host_cpu()
+    return {"value": 2 * sub.n_obj * n_freq / (c1 - c0), "unit": "trials/s",
+            "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"first {sub.n_obj} objects x all {n_freq} frequencies, SS and SSSP, "
+                      f"FP64 C oracle ({c1 - c0:.1f} s)",
+            "cpu_model": model, "logical_cpus": logical, "physical_cores": physical}
+
+
+def _oracle_configs(synth):
+    """The oracle on the single small object in full and on a sample of the
+    dense object's grid (the oracle fits every window explicitly, O(n b) per
+    smooth: the dense object's full grid would take hours)."""
+    import numpy as np
+    import oracle
+    out = {}
+    cat1, grid1 = synth.single_small()
+    c0 = time.perf_counter()
+    for m in (oracle.SS, oracle.SSSP):
+        oracle.periodogram(m, cat1.offsets, cat1.t, cat1.y, cat1.e, *grid1)
+    dt = time.perf_counter() - c0
+    out["single_small_full"] = {"s": dt, "trials_per_s": 2 * grid1[2] / dt,
+                                "trials": 2 * grid1[2], "threads": oracle.num_threads()}
+    cat3, grid3 = synth.single_dense()
+    ks = np.linspace(0, grid3[2] - 1, 48).astype(np.int64)
+    c0 = time.perf_counter()
+    for m in (oracle.SS, oracle.SSSP):
+        oracle.periodogram(m, cat3.offsets, cat3.t, cat3.y, cat3.e, *grid3, ks=ks)
+    dt = time.perf_counter() - c0
+    rate = 2 * ks.size / dt
+    out["single_dense_sample"] = {"s": dt, "trials_per_s": rate, "frequencies": int(ks.size),
+                                  "full_grid_s_extrapolated": 2 * grid3[2] / rate,
+                                  "threads": oracle.num_threads()}
+    return out
+
+
+def _shared_sampling(ctx, ssg, synth, n_obj=1000, n=200):
+    """Objects that share one time sampling: the shared-catalog call (one
+    fold and sort per frequency and batch) against the ordinary call on the
+    same objects, FP64, 20,000 frequencies, both methods."""
+    import numpy as np
+    import torch
+    rng = np.random.default_rng(17)
+    t = np.sort(rng.uniform(0, 1000.0, n))
+    cat = synth.make_catalog(17, n_obj, n, 1000.0, (0.2, 10.0), 0.05)
+    y = cat.y.reshape(n_obj, n)
+    e = cat.e.reshape(n_obj, n)
+    grid = (0.1, 10.0, 20_000)
+    sc = ssg.SharedCatalog.from_numpy(t, y, e)
+    dc = ssg.DeviceCatalog.from_numpy(np.arange(n_obj + 1, dtype=np.int64) * n,
+                                      np.tile(t, n_obj), y.ravel(), e.ravel())
+    out = {"catalog": f"{n_obj} objects x {n} points at one set of times, {grid[2]} "
+                      f"frequencies, FP64"}
+    for m, name in ((ssg.SS_METHOD_SS, "ss"), (ssg.SS_METHOD_SSSP, "sssp")):
+        r = {}
+        for label, fn in (("shared", lambda: ctx.shared_best_period(m, sc, grid)),
+                          ("ordinary", lambda: ctx.ss_best_period(m, dc, grid))):
+            res = fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res = fn()
+            torch.cuda.synchronize()
+            r[label] = n_obj * grid[2] / (time.perf_counter() - t0)
+        same = torch.equal(ctx.shared_best_period(m, sc, grid)[0],
+                           ctx.ss_best_period(m, dc, grid)[0])
+        out[name] = {"shared_trials_per_s": r["shared"], "ordinary_trials_per_s": r["ordinary"],
+                     "speedup": r["shared"] / r["ordinary"], "same_best_index": bool(same)}
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -266,7 +370,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", choices=("fp64", "fp32c"), default="fp64")
     ap.add_argument("--n-obj", type=int, default=10_000)
-    ap.add_argument("--cpu-sample-objects", type=int, default=24)
+    ap.add_argument("--cpu-sample-objects", type=int, default=100)
     ap.add_argument("--learned-objects", type=int, default=2000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
@@ -343,16 +447,7 @@ def main() -> int:
 
     cpu = None
     if not args.no_cpu_baseline:
-        import oracle
-        sub = cat.subset(np.arange(min(args.cpu_sample_objects, n_obj)))
-        c0 = time.perf_counter()
-        for m in (oracle.SS, oracle.SSSP):
-            oracle.periodogram(m, sub.offsets, sub.t, sub.y, sub.e, *grid)
-        c1 = time.perf_counter()
-        cpu = {"value": 2 * sub.n_obj * n_freq / (c1 - c0), "unit": "trials/s",
-               "cores": oracle.num_threads(), "kind": "oracle",
-               "sample": f"first {sub.n_obj} objects x all {n_freq} frequencies, SS and SSSP, "
-                         f"FP64 C oracle ({c1 - c0:.1f} s)"}
+        cpu = _cpu_baseline(cat, grid, args.cpu_sample_objects)
 
     rec = {
         "metric": "obj*freq trials/s (SS & SSSP, N=200)",
@@ -376,6 +471,9 @@ def main() -> int:
         "cpu_baseline": cpu,
         "extras": extras,
     }
+    if not args.no_cpu_baseline and not args.no_extras:
+        from paper_2111_07396_amd import synth as _s
+        rec["extras"]["oracle_configs"] = _oracle_configs(_s)
     print(json.dumps(rec), flush=True)
     ctx.close()
     return 0

@@ -263,11 +263,16 @@ int ss_shape_info(int index, int32_t *nw, int32_t *ppl);
 int ss_ctx_set_shape(ss_ctx *ctx, int32_t n_max, int32_t nw, int32_t ppl);
 int ss_ctx_set_tile(ss_ctx *ctx, int32_t tile_f);
 
+/* Whether the size classes of one call run concurrently (enable != 0:
+ * launches forked onto internal streams and joined back to the call's
+ * stream) or one after another on the call's stream (0, the default, which
+ * measured faster on MI355X). */
+int ss_ctx_set_concurrency(ss_ctx *ctx, int32_t enable);
+
 /* Kernel timing, for benchmarks.  With timing enabled, every call records HIP
- * events on its stream around each launch of the fused trial kernel; when a
- * call has several size classes, their launches run concurrently on internal
- * streams forked from and joined to the call's stream, and one pair of events
- * spans fork to join.  ss_ctx_trial_kernel_ms waits for the last call's events and
+ * events on its stream around each launch of the fused trial kernel; when
+ * concurrency is on (ss_ctx_set_concurrency) and a call has several size
+ * classes, one pair of events spans the fork to the join.  ss_ctx_trial_kernel_ms waits for the last call's events and
  * returns the summed duration of its trial-kernel launches in milliseconds
  * and their count.  Returns SS_ERR_INVALID_ARG if timing was off. */
 int ss_ctx_set_timing(ss_ctx *ctx, int enable);

@@ -35,7 +35,7 @@ EXPORTED = ("ss_params_default", "ss_ctx_create", "ss_ctx_destroy", "ss_periodog
             "ss_model_save", "ss_model_load", "ss_model_file_write", "ss_model_file_read",
             "ss_train_step", "ss_best_period_learned", "ss_model_copy_params",
             "ss_shared_periodogram", "ss_shared_best_period", "ss_plan_batches",
-            "ss_periodogram_batched", "ss_best_period_noalloc")
+            "ss_periodogram_batched", "ss_best_period_noalloc", "ss_ctx_set_concurrency")
 ENC_PARAMS = 145536
 ENC_BINS = 1024
 
@@ -123,6 +123,8 @@ def load_library(path: str = LIB_PATH):
     lib.ss_shape_info.restype = ctypes.c_int
     lib.ss_ctx_set_shape.argtypes = [vp, i32, i32, i32]
     lib.ss_ctx_set_shape.restype = ctypes.c_int
+    lib.ss_ctx_set_concurrency.argtypes = [vp, i32]
+    lib.ss_ctx_set_concurrency.restype = ctypes.c_int
     lib.ss_ctx_set_tile.argtypes = [vp, i32]
     lib.ss_ctx_set_tile.restype = ctypes.c_int
     lib.ss_ctx_set_timing.argtypes = [vp, ctypes.c_int]
@@ -343,6 +345,10 @@ class Context:
         """Objects with n <= n_max run on trial groups of nw waves x ppl points per thread
         (nw = 0 clears every rule)."""
         _check(_lib.ss_ctx_set_shape(self._h, int(n_max), int(nw), int(ppl)))
+
+    def set_concurrency(self, enable: bool = True):
+        """Run a call's size classes concurrently (forked streams) or serially."""
+        _check(_lib.ss_ctx_set_concurrency(self._h, int(bool(enable))))
 
     def set_tile(self, tile_f: int):
         """Trial frequencies per work item (0 = automatic)."""

@@ -18,10 +18,8 @@ __device__ __forceinline__ int pick_shape(const ShapeRules &R, int64_t n) {
 
 __global__ void reset_kernel(int32_t *counts, unsigned long long *queues, int n) {
     const int i = threadIdx.x;
-    if (i < n) {
-        counts[i] = 0;
-        queues[i] = 0ull;
-    }
+    if (i < n) counts[i] = 0;
+    for (int q = i; q < n * kQueuesPerClass; q += blockDim.x) queues[q] = 0ull;
 }
 
 // One wavefront per object.  FP64 throughout.  Status precedence: fewer than

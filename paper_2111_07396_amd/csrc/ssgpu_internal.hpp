@@ -24,7 +24,8 @@ struct TrialLaunch {
     Prepared cat;
     const int32_t *objs;         // object ids of this class (written by prep)
     const int32_t *count;        // number of objects in this class
-    unsigned long long *queue;   // next item to hand out (zeroed before prep)
+    unsigned long long *queue;   // kQueuesPerClass counters of items handed out
+                                 // (zeroed before prep)
     int32_t n_tiles;
     int32_t tile_f;
     double fmin, df;
@@ -51,6 +52,13 @@ struct TrialLaunch {
     const double *shared_tt;
 };
 constexpr int kMaxSharedBatch = 16;
+
+// Work queues per size class: one per XCD of MI355X (workgroups are dispatched
+// to the 8 XCDs in turn by workgroup id).  Queue q holds the items of the
+// class's objects with slot = q mod 8, so all frequency tiles of an object are
+// taken on one XCD and its data is fetched into that XCD's L2 once; a
+// workgroup whose own queue is empty takes from the others.
+constexpr int kQueuesPerClass = 8;
 
 // Expressions that must round exactly like their plain C statement (no
 // fused multiply-add), so that grid frequencies, window half-widths and the
@@ -102,8 +110,9 @@ struct ShapeRules {
     uint32_t runnable;  // bit per shape index
 };
 
-// Zeroes the per-class object counts and queue heads (a kernel, so that the
-// sequence stays valid inside a captured graph).
+// Zeroes the per-class object counts and the kQueuesPerClass queue heads of
+// each class (a kernel, so that the sequence stays valid inside a captured
+// graph).
 hipError_t launch_reset(int32_t *counts, unsigned long long *queues, int n, hipStream_t stream);
 
 // Prep plus planning: status, tt/w/yc, chi0, and the object's entry in its

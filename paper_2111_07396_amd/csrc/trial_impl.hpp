@@ -1352,9 +1352,9 @@ constexpr int waves_per_simd() {
     return 1;
 }
 
-// Persistent: every workgroup takes items from the class queue until all
-// count * n_tiles items are handed out (each workgroup exits after at most
-// one failed take).
+// Persistent: every workgroup takes items from the class's queues until all
+// count * n_tiles items are handed out (each workgroup exits after one failed
+// take per queue).
 template <class P, int NW, int PPL, int METHOD, bool PDM, bool SHARED = false>
 __global__ __launch_bounds__(kWave *NW,
                              (PDM ? 1 : waves_per_simd<P::kIsF64, NW, PPL, METHOD>()))
@@ -1376,21 +1376,37 @@ void trial_kernel(TrialLaunch L) {
     G.inv_n = 0.0;
     G.inv_chi0 = 0.0;
     G.n = 0;
+    // units: the class's objects (or batches of objects sharing their times);
+    // queue q hands out the (unit, tile) items of the units with u mod
+    // kQueuesPerClass == q, all tiles of a unit in a row.  A workgroup starts
+    // on the queue of its XCD and moves on to the next when one is empty, so
+    // every workgroup exits after one failed take per queue.
     const unsigned long long units =
         SHARED ? (unsigned long long)((*L.count + L.shared_batch - 1) / L.shared_batch)
                : (unsigned long long)(*L.count);
-    const unsigned long long total = units * (unsigned long long)L.n_tiles;
+    const unsigned long long n_tiles = (unsigned long long)L.n_tiles;
     unsigned long long *take = (unsigned long long *)(lds + Y.qslot);
-    for (;;) {
-        bsync<NW>();
-        if (G.t == 0) *take = atomicAdd(L.queue, 1ull);
-        bsync<NW>();
-        const unsigned long long item = *take;
-        if (item >= total) break;
-        if constexpr (SHARED)
-            run_item_shared<P, NW, PPL, METHOD>(G, lds, Y, L, (int64_t)item);
-        else
-            run_item<P, NW, PPL, METHOD, PDM>(G, lds, Y, L, (int64_t)item);
+    const int own = (int)(blockIdx.x % kQueuesPerClass);
+    for (int k = 0; k < kQueuesPerClass; ++k) {
+        const int q = (own + k) % kQueuesPerClass;
+        const unsigned long long uq =
+            units > (unsigned long long)q
+                ? (units - q + kQueuesPerClass - 1) / kQueuesPerClass
+                : 0ull;
+        const unsigned long long total = uq * n_tiles;
+        for (;;) {
+            bsync<NW>();
+            if (G.t == 0) *take = atomicAdd(L.queue + q, 1ull);
+            bsync<NW>();
+            const unsigned long long local = *take;
+            if (local >= total) break;
+            const unsigned long long unit = q + kQueuesPerClass * (local / n_tiles);
+            const int64_t item = (int64_t)(unit * n_tiles + local % n_tiles);
+            if constexpr (SHARED)
+                run_item_shared<P, NW, PPL, METHOD>(G, lds, Y, L, item);
+            else
+                run_item<P, NW, PPL, METHOD, PDM>(G, lds, Y, L, item);
+        }
     }
 }
 

@@ -1,8 +1,9 @@
 """Batching: the Eq. 1 memory planner (Sec. 4.1) splits a periodogram into
 object batches that fit beta times the device memory; forced small budgets
 give many batches whose rows are bit for bit the one-call periodogram.
-Catalogs with several length classes run their class launches concurrently
-(forked streams), with results equal to the oracle."""
+A catalog with several length classes gives the same results with its class
+launches forked onto concurrent streams and run one after another, equal to
+the oracle."""
 import numpy as np
 import pytest
 
@@ -71,13 +72,20 @@ def test_concurrent_classes_match_oracle(ctx):
     ctx.set_timing(True)
     try:
         for method in (oracle.SS, oracle.SSSP):
+            ctx.set_concurrency(True)
             pg, st = ctx.method_periodogram(method, dc, grid)
             ms, n_launch = ctx.trial_kernel_ms()
             torch.cuda.synchronize()
             assert n_launch == 1 and ms > 0  # one span, fork to join
+            ctx.set_concurrency(False)
+            pg_serial, _ = ctx.method_periodogram(method, dc, grid)
+            torch.cuda.synchronize()
+            assert ctx.trial_kernel_ms()[1] > 1  # one span per class launch
+            np.testing.assert_array_equal(pg.cpu().numpy(), pg_serial.cpu().numpy())
             po, so = oracle.periodogram(method, offs, t, y, e, *grid)
             pg = pg.cpu().numpy()
             d = np.abs(pg - po)
             assert np.all(d <= 1e-4 * np.maximum(1 - po, 1e-12) + 1e-12)
     finally:
         ctx.set_timing(False)
+        ctx.set_concurrency(False)
