@@ -255,6 +255,13 @@ def _proposal(ctx, ssg, synth, args):
             t_full=t_full)
         rl["encoder_only"] = learn.compare(ctx, dc5, grid5, w, 0.0, pol["top_k"], pol["margin"],
                                            pol["full_below"], full=full5, t_full=t_full)
+    bs = rl["bin_scores_then_refine"]
+    rl["target_10x_at_99pct"] = {
+        "met_by_bin_scores": bool(bs["agreement"] >= 0.99 and bs["speedup"] >= 10.0),
+        "met_by_learned_network": False,
+        "note": "the set encoder alone agrees on ~36 % of objects; added to the bin scores it "
+                "does not raise the agreement, so the >= 10x at >= 99 % result comes from the "
+                "non-learned exact-grid bin scores, not from the network"}
     ex["proposal_vs_full"] = rl
     ex["proposal_kernels"] = _proposal_kernels(ctx, ssg, dc5, grid5, cat5)
     return ex

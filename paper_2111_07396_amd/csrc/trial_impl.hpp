@@ -1394,6 +1394,7 @@ void trial_kernel(TrialLaunch L) {
                 ? (units - q + kQueuesPerClass - 1) / kQueuesPerClass
                 : 0ull;
         const unsigned long long total = uq * n_tiles;
+        if (total == 0) continue;  // an empty queue needs no take
         for (;;) {
             bsync<NW>();
             if (G.t == 0) *take = atomicAdd(L.queue + q, 1ull);

@@ -6,9 +6,12 @@ full grid of proposals refined by the exact search (untrained and trained
 encoder alone, bin scores alone, both).  The pass bars are what this design
 reaches: training lowers the loss and raises the held-out recall and the
 encoder-only agreement over the untrained network, and the bin-score
-proposal reaches >= 99 % agreement.  The encoder's sin/cos features cannot
-place a period to the grid's resolution, so adding its logits to the bin
-scores is reported, not required to help."""
+proposal reaches >= 99 % agreement, and adding the trained network's logits
+to the bin scores at the benchmark's weighting (100 x the scores) must not
+lower the agreement by more than 0.5 %.  The encoder's sin/cos features
+cannot place a period to the grid's resolution, so the network is not
+required to raise the agreement: it does not, and the learned proposal
+target (>= 10x at >= 99 % from the network) is not met by this design."""
 import numpy as np
 import pytest
 
@@ -42,15 +45,16 @@ def test_training_and_proposal_gain():
     pol = dict(learn.POLICY)
     full = ctx.ss_best_period(0, held, grid)
     a_scores = learn.compare(ctx, held, grid, None, repeats=1, full=full, **pol)["agreement"]
-    a_both = learn.compare(ctx, held, grid, p, 10.0, pol["top_k"], pol["margin"],
+    a_both = learn.compare(ctx, held, grid, p, 100.0, pol["top_k"], pol["margin"],
                            pol["full_below"], repeats=1, full=full)["agreement"]
     a_enc = learn.compare(ctx, held, grid, p, 0.0, pol["top_k"], pol["margin"],
                           pol["full_below"], repeats=1, full=full)["agreement"]
     a_enc0 = learn.compare(ctx, held, grid, p0, 0.0, pol["top_k"], pol["margin"],
                            pol["full_below"], repeats=1, full=full)["agreement"]
     print(f"agreement with the full grid: untrained encoder {a_enc0:.4f}, trained encoder "
-          f"{a_enc:.4f}, bin scores {a_scores:.4f}, trained encoder + 10 x bin scores "
+          f"{a_enc:.4f}, bin scores {a_scores:.4f}, trained encoder + 100 x bin scores "
           f"{a_both:.4f}")
     assert a_enc > a_enc0
     assert a_scores >= 0.99
+    assert a_both >= a_scores - 0.005
     ctx.close()
