@@ -248,6 +248,10 @@ def _proposal(ctx, ssg, synth, args):
           "policy": pol}
     rl["bin_scores_then_refine"] = learn.compare(ctx, dc5, grid5, None, full=full5,
                                                  t_full=t_full, **pol)
+    # the same comparison in the compensated-FP32 precision of the mixed stream's
+    # configuration (full grid and refine both in FP32c)
+    rl["bin_scores_then_refine_fp32c"] = learn.compare(ctx, dc5, grid5, None,
+                                                       precision=ssg.SS_FP32C, **pol)
     if os.path.exists(ENCODER_WEIGHTS):
         w = torch.tensor(np.load(ENCODER_WEIGHTS), dtype=torch.float32, device="cuda")
         rl["encoder_plus_100x_bin_scores"] = learn.compare(

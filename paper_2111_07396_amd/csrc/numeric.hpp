@@ -100,6 +100,13 @@ __device__ __forceinline__ df wave_incl_sum_df(df x) {
     return x;
 }
 
+// Cross-row scan temporaries of the FP64 policy (wave_incl_sum_z); the
+// float-pair policy clears its own.
+struct ScanZ64 {
+    double z15 = 0.0, z31 = 0.0;
+};
+struct ScanZNone {};
+
 // ------------------------------------------------------------------ policies
 struct F64 {
     using R = double;  // per-point values
@@ -118,7 +125,8 @@ struct F64 {
     __device__ static double dbl(S a) { return a; }
     __device__ static S zero() { return 0.0; }
     __device__ static S quot(S a, S /*b*/, R ib) { return a * ib; }
-    __device__ static S scan(S x) { return wave_incl_sum(x); }
+    using Z = ScanZ64;
+    __device__ static S scan(S x, Z &z) { return wave_incl_sum_z(x, z.z15, z.z31); }
     __device__ static S lane_value(S x, int lane) { return readlane_f64(x, lane); }
     __device__ static R rcp(R a) { return rcp64(a); }
     __device__ static R fabs_(R a) { return fabs(a); }
@@ -171,7 +179,8 @@ struct F32C {
         float q2 = r.hi * ib;
         return fast_two_sum(q1, q2);
     }
-    __device__ static S scan(S x) { return wave_incl_sum_df(x); }
+    using Z = ScanZNone;
+    __device__ static S scan(S x, Z &) { return wave_incl_sum_df(x); }
     __device__ static S lane_value(S x, int lane) { return readlane_df(x, lane); }
     __device__ static R rcp(R a) { return __builtin_amdgcn_rcpf(a); }
     __device__ static R fabs_(R a) { return fabsf(a); }

@@ -70,9 +70,13 @@ __host__ __device__ __forceinline__ double grid_freq(double fmin, double df, int
     return fmin + step;
 }
 
+// 0.5 span n + 0.5, with the product formed as span (n / 2): halving is exact,
+// so this is the same rounded product as (0.5 span) n, and no factor of it
+// is invariant across work items (a hoisted 0.5 span was held in registers
+// for the whole kernel).
 __host__ __device__ __forceinline__ double halfwidth_real(double span, int n) {
 #pragma clang fp contract(off)
-    return 0.5 * span * (double)n + 0.5;
+    return span * (0.5 * (double)n) + 0.5;
 }
 
 __host__ __device__ __forceinline__ double listing_vsmlsq(double scale) {

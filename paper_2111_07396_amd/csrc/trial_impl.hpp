@@ -111,9 +111,11 @@ struct Group {
     S *xs;                   // exchange slots for group scans
     double *xd;              // exchange slots for group sums
     int t, wave, lane, n, ext;
+    int hw[3], hwf;          // half-widths of the spans and of the fixed span at n
     double vsmlsq;
     double inv_n, inv_chi0;  // 1/n and 1/chi0 of the work item's object
     bool ties;
+    mutable typename P::Z z;  // cross-row scan temporaries (see wave_incl_sum_z)
     // first value of prefix slot i (i = -ext .. n + ext)
     __device__ int at(int i) const { return qaddr<F, PPL>(ext + i); }
     // scratch array k (0..2) of NT * PPL values of type R
@@ -145,11 +147,35 @@ __device__ __forceinline__ typename P::R bass_pow(typename P::R tmp, typename P:
 }
 
 // ------------------------------------------------------------------ group reductions
+// Sum over the wavefront (all lanes active), identical in every lane.
+template <class P, int NW, int PPL, int F>
+__device__ __forceinline__ double wave_total(const Group<P, NW, PPL, F> &G, double a) {
+    if constexpr (P::kIsF64) {
+        return readlane_f64(wave_incl_sum_z(a, G.z.z15, G.z.z31), kWave - 1);
+    } else {
+        return wave_sum(a);
+    }
+}
+
+// Sum over the group of one double, identical in every thread.
+template <class P, int NW, int PPL, int F>
+__device__ __forceinline__ double group_sum1(const Group<P, NW, PPL, F> &G, double a) {
+    a = wave_total(G, a);
+    if constexpr (NW > 1) {
+        if (G.lane == 0) G.xd[G.wave] = a;
+        __syncthreads();
+        a = 0.0;
+        for (int w = 0; w < NW; ++w) a += G.xd[w];
+        __syncthreads();
+    }
+    return a;
+}
+
 // Sum over the group of two doubles, identical in every thread.
 template <class P, int NW, int PPL, int F>
 __device__ __forceinline__ void group_sum2(const Group<P, NW, PPL, F> &G, double &a, double &b) {
-    a = wave_sum(a);
-    b = wave_sum(b);
+    a = wave_total(G, a);
+    b = wave_total(G, b);
     if constexpr (NW > 1) {
         if (G.lane == 0) {
             G.xd[2 * G.wave] = a;
@@ -174,7 +200,7 @@ __device__ __forceinline__ void group_excl(const Group<P, NW, PPL, F> &G,
     using S = typename P::S;
     S incl[M];
 #pragma unroll
-    for (int m = 0; m < M; ++m) incl[m] = P::scan(tot[m]);
+    for (int m = 0; m < M; ++m) incl[m] = P::scan(tot[m], G.z);
     if constexpr (NW == 1) {
 #pragma unroll
         for (int m = 0; m < M; ++m) {
@@ -189,14 +215,23 @@ __device__ __forceinline__ void group_excl(const Group<P, NW, PPL, F> &G,
         __syncthreads();
 #pragma unroll
         for (int m = 0; m < M; ++m) {
-            S off = P::zero(), sum = P::zero();
-            for (int w = 0; w < NW; ++w) {
-                const S v = G.xs[m * NW + w];
-                if (w < G.wave) off = P::add(off, v);
-                sum = P::add(sum, v);
+            if constexpr (NW == 2 && P::kIsF64) {
+                // the first wavefront's total is added by the second only:
+                // an FMA with the (wave-uniform) factor 1 or 0 is that add
+                // exactly, or nothing
+                const S v0 = G.xs[m * 2], v1 = G.xs[m * 2 + 1];
+                excl[m] = fma(v0, G.wave ? 1.0 : 0.0, incl[m] - tot[m]);
+                all[m] = v0 + v1;
+            } else {
+                S off = P::zero(), sum = P::zero();
+                for (int w = 0; w < NW; ++w) {
+                    const S v = G.xs[m * NW + w];
+                    if (w < G.wave) off = P::add(off, v);
+                    sum = P::add(sum, v);
+                }
+                excl[m] = P::add(off, P::sub(incl[m], tot[m]));
+                all[m] = sum;
             }
-            excl[m] = P::add(off, P::sub(incl[m], tot[m]));
-            all[m] = sum;
         }
     }
 }
@@ -547,9 +582,7 @@ __device__ __forceinline__ double chi2_of(const Group<P, NW, PPL, F> &G,
         const R d = G.t * PPL + p < G.n ? y[p] - smo[p] : R(0);
         acc = P::add(acc, P::prod(w[p] * d, d));
     }
-    double a = P::dbl(acc), z = 0.0;
-    group_sum2<P, NW, PPL>(G, a, z);
-    return a;
+    return group_sum1<P, NW, PPL>(G, P::dbl(acc));
 }
 
 // Smooth of v with a stored geometry (phase B): prefix pair (BUF as in
@@ -649,7 +682,7 @@ __device__ double supersmoother(const Group<P, NW, PPL, F> &G, const TrialLaunch
     using Geo = typename P::Geo;
     const int n = G.n, t = G.t;
     if (L.fixed_span > 0.0) {  // Listing 1: one smooth at the fixed span
-        const int b = halfwidth(n, L.fixed_span);
+        const int b = G.hwf;
         Geo g[PPL];
         R smo[PPL];
         prefix_x<P, NW, PPL>(G, x, w, wx, b);
@@ -661,8 +694,7 @@ __device__ double supersmoother(const Group<P, NW, PPL, F> &G, const TrialLaunch
         smooth_with<P, NW, PPL>(G, b, g, w, wx, y, b, smo);
         return chi2_of<P, NW, PPL>(G, w, y, smo);
     }
-    const int b0 = halfwidth(n, L.span[0]), b1 = halfwidth(n, L.span[1]),
-              b2 = halfwidth(n, L.span[2]);
+    const int b0 = G.hw[0], b1 = G.hw[1], b2 = G.hw[2];
     const R sp0 = (R)L.span[0], sp1 = (R)L.span[1], sp2 = (R)L.span[2];
 
     Geo g0[PPL], g1[PPL];
@@ -827,7 +859,7 @@ __device__ double single_pass(const Group<P, NW, PPL, F> &G, const TrialLaunch &
     const int n = G.n, t = G.t;
     const int K = L.fixed_span > 0.0 ? 1 : 3;
     int b[3];
-    for (int k = 0; k < 3; ++k) b[k] = halfwidth(n, K == 1 ? L.fixed_span : L.span[k]);
+    for (int k = 0; k < 3; ++k) b[k] = K == 1 ? G.hwf : G.hw[k];
     int e = b[0];
     for (int k = 1; k < K; ++k) e = b[k] > e ? b[k] : e;
     // A1: geometry of every candidate span, and the smoother traces
@@ -863,9 +895,9 @@ __device__ double single_pass(const Group<P, NW, PPL, F> &G, const TrialLaunch &
     }
     if constexpr (GV) {
         if (K == 3) {
-            double trd[3] = {P::dbl(tr[0]), P::dbl(tr[1]), P::dbl(tr[2])}, z = 0.0;
+            double trd[3] = {P::dbl(tr[0]), P::dbl(tr[1]), P::dbl(tr[2])};
             group_sum2<P, NW, PPL>(G, trd[0], trd[1]);
-            group_sum2<P, NW, PPL>(G, trd[2], z);
+            trd[2] = group_sum1<P, NW, PPL>(G, trd[2]);
             bool ok[3];
             R iden[3];
 #pragma unroll
@@ -973,7 +1005,7 @@ __device__ double pdm_score(const Group<P, NW, PPL, F> &G, int B, const typename
     build_prefix<P, NW, PPL, 2, false>(G, Pf, q, T);
     const int n = G.n;
     const uint64_t one = 1ull << 48;
-    double e = 0.0, z = 0.0;
+    double e = 0.0;
     for (int b = G.t; b < B; b += Group<P, NW, PPL, F>::NT) {
         const int lo = count_below(G.SK, n, ((uint64_t)b * one + (uint64_t)(B - 1)) / (uint64_t)B);
         const int hi = b == B - 1 ? n
@@ -984,8 +1016,7 @@ __device__ double pdm_score(const Group<P, NW, PPL, F> &G, int B, const typename
         const double sb = P::dbl(P::sub(G.Q[G.at(hi) + 1], G.Q[G.at(lo) + 1]));
         if (wb > 0.0) e += sb * sb / wb;
     }
-    group_sum2<P, NW, PPL>(G, e, z);
-    return e / chi0;
+    return group_sum1<P, NW, PPL>(G, e) / chi0;
 }
 
 // ------------------------------------------------------------------ one trial
@@ -1166,6 +1197,16 @@ __device__ double run_trial(Group<P, NW, PPL, F> &G, unsigned char *lds, const L
                                                          pdm);
 }
 
+// Per-length values of a work item, once per item (the trials multiply by
+// 1/n; the half-widths are taken here rather than per trial).
+template <class P, int NW, int PPL, int F>
+__device__ __forceinline__ void set_length(Group<P, NW, PPL, F> &G, const TrialLaunch &L, int n) {
+    G.n = n;
+    G.inv_n = 1.0 / (double)n;
+    for (int k = 0; k < 3; ++k) G.hw[k] = halfwidth(n, L.span[k]);
+    G.hwf = L.fixed_span > 0.0 ? halfwidth(n, L.fixed_span) : 0;
+}
+
 // One work item: an object and a run of consecutive trial frequencies (a tile
 // of the full grid, or one refine range).
 template <class P, int NW, int PPL, int METHOD, bool PDM, int F>
@@ -1200,13 +1241,12 @@ __device__ void run_item(Group<P, NW, PPL, F> &G, unsigned char *lds, const Layo
         return;
     }
     const int64_t base = L.cat.offsets[obj];
-    G.n = (int)(L.cat.offsets[obj + 1] - base);
+    set_length(G, L, (int)(L.cat.offsets[obj + 1] - base));
     ObjData<P> od;
     od.tt = L.cat.tt + base;
     od.y = (P::kIsF64 ? (const R *)L.cat.yc : (const R *)L.cat.yc32) + base;
     od.w = (P::kIsF64 ? (const R *)L.cat.w : (const R *)L.cat.w32) + base;
     const double chi0 = L.cat.chi0[obj];
-    G.inv_n = 1.0 / (double)G.n;  // once per item: the trials multiply
     G.inv_chi0 = 1.0 / chi0;
     if constexpr (caches_object(kWave * NW * PPL)) {
         double *ct = (double *)(lds + Y.obj);
@@ -1280,8 +1320,7 @@ __device__ void run_item_shared(Group<P, NW, PPL, F> &G, unsigned char *lds, con
         }
         return;
     }
-    G.n = L.shared_n;
-    G.inv_n = 1.0 / (double)G.n;
+    set_length(G, L, L.shared_n);
     constexpr bool kCache = caches_object(kWave * NW * PPL);
     if constexpr (kCache) {
         double *ct = (double *)(lds + Y.obj);
@@ -1368,7 +1407,7 @@ void trial_kernel(TrialLaunch L) {
     G.xs = (S *)(lds + Y.xch);
     G.xd = (double *)(lds + Y.xch);
     G.t = threadIdx.x;
-    G.wave = threadIdx.x / kWave;
+    G.wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // uniform per wavefront
     G.lane = threadIdx.x % kWave;
     G.ext = Y.ext;
     G.ties = false;
@@ -1376,6 +1415,8 @@ void trial_kernel(TrialLaunch L) {
     G.inv_n = 0.0;
     G.inv_chi0 = 0.0;
     G.n = 0;
+    for (int k = 0; k < 3; ++k) G.hw[k] = 0;
+    G.hwf = 0;
     // units: the class's objects (or batches of objects sharing their times);
     // queue q hands out the (unit, tile) items of the units with u mod
     // kQueuesPerClass == q, all tiles of a unit in a row.  A workgroup starts

@@ -50,6 +50,33 @@ __device__ __forceinline__ double wave_incl_sum(double x) {
     return x;
 }
 
+// The same scan with the two cross-row steps writing into caller-held
+// temporaries z15, z31 that start at 0.0: a row_bcast step writes only the
+// rows it adds to (rows 1, 3 and rows 2, 3), so the other rows of its
+// temporary stay 0 from one scan to the next and need no clearing.  Every
+// lane must be active (an inactive source lane would leave a stale value).
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_f64_into(double old, double v) {
+    const uint64_t uo = __builtin_bit_cast(uint64_t, old), uv = __builtin_bit_cast(uint64_t, v);
+    const int lo = __builtin_amdgcn_update_dpp((int)(uint32_t)uo, (int)(uint32_t)uv, CTRL,
+                                               ROWMASK, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp((int)(uint32_t)(uo >> 32), (int)(uint32_t)(uv >> 32),
+                                               CTRL, ROWMASK, 0xf, false);
+    return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo);
+}
+
+__device__ __forceinline__ double wave_incl_sum_z(double x, double &z15, double &z31) {
+    x += dpp_f64<0x111, 0xf, true>(x);
+    x += dpp_f64<0x112, 0xf, true>(x);
+    x += dpp_f64<0x114, 0xf, true>(x);
+    x += dpp_f64<0x118, 0xf, true>(x);
+    z15 = dpp_f64_into<0x142, 0xa>(z15, x);
+    x += z15;
+    z31 = dpp_f64_into<0x143, 0xc>(z31, x);
+    x += z31;
+    return x;
+}
+
 __device__ __forceinline__ uint32_t wave_incl_sum_u32(uint32_t v) {
     int x = (int)v;
     x += dpp_i32<0x111, 0xf, true>(x);
