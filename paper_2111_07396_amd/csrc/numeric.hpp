@@ -127,6 +127,12 @@ struct F64 {
     __device__ static S quot(S a, S /*b*/, R ib) { return a * ib; }
     using Z = ScanZ64;
     __device__ static S scan(S x, Z &z) { return wave_incl_sum_z(x, z.z15, z.z31); }
+    template <int M>
+    __device__ static void scan_n(const S (&x)[M], S (&out)[M], Z &z) {
+#pragma unroll
+        for (int m = 0; m < M; ++m) out[m] = x[m];
+        wave_incl_sum_z_multi<M>(out, z.z15, z.z31);
+    }
     __device__ static S lane_value(S x, int lane) { return readlane_f64(x, lane); }
     __device__ static R rcp(R a) { return rcp64(a); }
     __device__ static R fabs_(R a) { return fabs(a); }
@@ -181,6 +187,11 @@ struct F32C {
     }
     using Z = ScanZNone;
     __device__ static S scan(S x, Z &) { return wave_incl_sum_df(x); }
+    template <int M>
+    __device__ static void scan_n(const S (&x)[M], S (&out)[M], Z &) {
+#pragma unroll
+        for (int m = 0; m < M; ++m) out[m] = wave_incl_sum_df(x[m]);
+    }
     __device__ static S lane_value(S x, int lane) { return readlane_df(x, lane); }
     __device__ static R rcp(R a) { return __builtin_amdgcn_rcpf(a); }
     __device__ static R fabs_(R a) { return fabsf(a); }

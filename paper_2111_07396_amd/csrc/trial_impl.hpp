@@ -70,9 +70,10 @@ constexpr __host__ __device__ int prefix_arrays(int method, int nw, int ppl) {
 
 // LDS layout of one trial group; identical on host and device.  The prefix
 // region starts at 0 and also serves as scratch of three arrays of np values
-// (tie averaging, CV fallbacks), and as the sort's counters and keys.
+// (tie averaging, CV fallbacks), and as the sort's bucketed keys.  The sort's
+// bucket counters have a region of their own, kept zero between trials.
 struct Layout {
-    int np, ext, F, qbytes, sk, xch, qslot, best, obj, bytes;
+    int np, ext, F, qbytes, sk, xch, qslot, best, obj, cnt, bytes;
     __host__ __device__ Layout(int nw, int ppl, int ext_, int method) {
         np = kWave * nw * ppl;
         ext = ext_;
@@ -82,16 +83,31 @@ struct Layout {
         int nd = (ulen - 1) * F + ((ulen - 1) / ppl) * pad_q(F, ppl) + F;  // values
         if (nd < 3 * np) nd = 3 * np;
         qbytes = (nd * 8 + 15) / 16 * 16;
-        const int sort_end = ((np + 1) * 4 + 15) / 16 * 16 + (cache ? 1 : 3) * np * 8;
+        const int sort_end = (cache ? 1 : 3) * np * 8;
         int a = qbytes > sort_end ? qbytes : sort_end;
         sk = (a + 15) / 16 * 16;
         xch = sk + np * 8;
         qslot = xch + nw * 8 * 8;
         best = qslot + 16;
         obj = best + kMaxSharedBatch * 12;
-        bytes = obj + (cache ? 3 * np * 8 : 0);
+        cnt = obj + (cache ? 3 * np * 8 : 0);
+        bytes = cnt + ((np + 1) * 4 + 15) / 16 * 16;
     }
 };
+
+// A value loaded at a wave-uniform address, made a scalar (so that the
+// addresses formed from it live in scalar registers).
+__device__ __forceinline__ int uniform_i32(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t uniform_i64(int64_t v) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+template <class T>
+__device__ __forceinline__ const T *uniform_ptr(const T *p) {
+    return (const T *)uniform_i64((int64_t)p);
+}
 
 template <int NW>
 __device__ __forceinline__ void bsync() {
@@ -112,6 +128,7 @@ struct Group {
     double *xd;              // exchange slots for group sums
     int t, wave, lane, n, ext;
     int hw[3], hwf;          // half-widths of the spans and of the fixed span at n
+    typename P::R ilo, ihi;  // 1/(span0 - span1), 1/(span2 - span1) of the blend
     double vsmlsq;
     double inv_n, inv_chi0;  // 1/n and 1/chi0 of the work item's object
     bool ties;
@@ -171,6 +188,23 @@ __device__ __forceinline__ double group_sum1(const Group<P, NW, PPL, F> &G, doub
     return a;
 }
 
+// The same for the last reduction of a trial (its chi^2): exchange slots of
+// their own (3 NW .. 4 NW, used by nothing else) and no trailing barrier -- the
+// next writer of these slots is the next trial's chi^2 sum, behind the
+// barriers of its sort and smoother.
+template <class P, int NW, int PPL, int F>
+__device__ __forceinline__ double group_sum1_last(const Group<P, NW, PPL, F> &G, double a) {
+    a = wave_total(G, a);
+    if constexpr (NW > 1) {
+        double *x = G.xd + 3 * NW;
+        if (G.lane == 0) x[G.wave] = a;
+        __syncthreads();
+        a = 0.0;
+        for (int w = 0; w < NW; ++w) a += x[w];
+    }
+    return a;
+}
+
 // Sum over the group of two doubles, identical in every thread.
 template <class P, int NW, int PPL, int F>
 __device__ __forceinline__ void group_sum2(const Group<P, NW, PPL, F> &G, double &a, double &b) {
@@ -193,14 +227,16 @@ __device__ __forceinline__ void group_sum2(const Group<P, NW, PPL, F> &G, double
 }
 
 // Exclusive prefix over the group's threads of M values; also the totals.
-template <class P, int NW, int PPL, int M, int F>
+// XO: first exchange slot (consecutive builds without a barrier between them
+// use disjoint slots).
+template <class P, int NW, int PPL, int M, int F, int XO = 0>
 __device__ __forceinline__ void group_excl(const Group<P, NW, PPL, F> &G,
                                            const typename P::S (&tot)[M],
                                            typename P::S (&excl)[M], typename P::S (&all)[M]) {
     using S = typename P::S;
+    S *const xs = G.xs + XO;
     S incl[M];
-#pragma unroll
-    for (int m = 0; m < M; ++m) incl[m] = P::scan(tot[m], G.z);
+    P::template scan_n<M>(tot, incl, G.z);
     if constexpr (NW == 1) {
 #pragma unroll
         for (int m = 0; m < M; ++m) {
@@ -210,7 +246,7 @@ __device__ __forceinline__ void group_excl(const Group<P, NW, PPL, F> &G,
     } else {
         if (G.lane == kWave - 1) {
 #pragma unroll
-            for (int m = 0; m < M; ++m) G.xs[m * NW + G.wave] = incl[m];
+            for (int m = 0; m < M; ++m) xs[m * NW + G.wave] = incl[m];
         }
         __syncthreads();
 #pragma unroll
@@ -219,13 +255,13 @@ __device__ __forceinline__ void group_excl(const Group<P, NW, PPL, F> &G,
                 // the first wavefront's total is added by the second only:
                 // an FMA with the (wave-uniform) factor 1 or 0 is that add
                 // exactly, or nothing
-                const S v0 = G.xs[m * 2], v1 = G.xs[m * 2 + 1];
+                const S v0 = xs[m * 2], v1 = xs[m * 2 + 1];
                 excl[m] = fma(v0, G.wave ? 1.0 : 0.0, incl[m] - tot[m]);
                 all[m] = v0 + v1;
             } else {
                 S off = P::zero(), sum = P::zero();
                 for (int w = 0; w < NW; ++w) {
-                    const S v = G.xs[m * NW + w];
+                    const S v = xs[m * NW + w];
                     if (w < G.wave) off = P::add(off, v);
                     sum = P::add(sum, v);
                 }
@@ -237,7 +273,8 @@ __device__ __forceinline__ void group_excl(const Group<P, NW, PPL, F> &G,
 }
 
 // Exclusive prefix sums P[i] = sum_{j<i} v_j of M quantities at slots
-// 0..n (padding points contribute 0); returns the totals.  Ends with a sync.
+// 0..n (padding points contribute 0); returns the totals.  Ends with a sync
+// (TRAIL; without it a later build's barrier must order the writes).
 // EXT: the arrays are the x-moment prefix (W, X, XX; M = 3) or a prefix pair
 // (V, XV of w v and w x v; M = 2), and their periodic extension by e slots
 // per side is written with them: each thread writes the copies of its own
@@ -246,7 +283,7 @@ __device__ __forceinline__ void group_excl(const Group<P, NW, PPL, F> &G,
 //   left:  P(-k) = P(n-k) - T  with the copy's phase shifted by -1,
 // so that X and XX pick up the terms of (x +- 1) and (x +- 1)^2.  Slots past
 // n + e are left unwritten (no window reaches them).
-template <class P, int NW, int PPL, int M, bool EXT, int F>
+template <class P, int NW, int PPL, int M, bool EXT, int F, bool TRAIL = true, int XO = 0>
 __device__ __forceinline__ void build_prefix(const Group<P, NW, PPL, F> &G,
                                              typename P::S *const (&Pf)[M],
                                              const typename P::S (&v)[M][PPL],
@@ -265,7 +302,7 @@ __device__ __forceinline__ void build_prefix(const Group<P, NW, PPL, F> &G,
         }
         tot[m] = acc;
     }
-    group_excl<P, NW, PPL, M>(G, tot, excl, T);
+    group_excl<P, NW, PPL, M, F, XO>(G, tot, excl, T);
     const int n = G.n;
 #pragma unroll
     for (int p = 0; p < PPL; ++p) {
@@ -311,7 +348,7 @@ __device__ __forceinline__ void build_prefix(const Group<P, NW, PPL, F> &G,
 #pragma unroll
         for (int m = 0; m < M; ++m) Pf[m][G.at(0)] = P::zero();
     }
-    bsync<NW>();
+    if constexpr (TRAIL) bsync<NW>();
 }
 
 // Periodic extension of the x-moment prefix (W, X, XX) by e slots per side.
@@ -536,24 +573,6 @@ __device__ void cv_fallback(const Group<P, NW, PPL, F> &G, bool any, typename P:
     bsync<NW>();
 }
 
-// Whether any point has a negative (marked) residual in any of three arrays.
-template <class P, int NW, int PPL, int F>
-__device__ __forceinline__ bool group_any_neg3(const Group<P, NW, PPL, F> &G,
-                                               const typename P::R (&r0)[PPL],
-                                               const typename P::R (&r1)[PPL],
-                                               const typename P::R (&r2)[PPL]) {
-    using R = typename P::R;
-    bool bad = false;
-#pragma unroll
-    for (int p = 0; p < PPL; ++p)
-        bad |= (G.t * PPL + p < G.n) && (r0[p] < R(0) || r1[p] < R(0) || r2[p] < R(0));
-    if constexpr (NW == 1) {
-        return wave_ballot(bad) != 0;
-    } else {
-        return __syncthreads_or(bad) != 0;
-    }
-}
-
 // Whether any point of the group has a negative (marked) residual.
 template <class P, int NW, int PPL, int F>
 __device__ __forceinline__ bool group_any_neg(const Group<P, NW, PPL, F> &G,
@@ -582,7 +601,7 @@ __device__ __forceinline__ double chi2_of(const Group<P, NW, PPL, F> &G,
         const R d = G.t * PPL + p < G.n ? y[p] - smo[p] : R(0);
         acc = P::add(acc, P::prod(w[p] * d, d));
     }
-    return group_sum1<P, NW, PPL>(G, P::dbl(acc));
+    return group_sum1_last<P, NW, PPL>(G, P::dbl(acc));
 }
 
 // Smooth of v with a stored geometry (phase B): prefix pair (BUF as in
@@ -634,7 +653,10 @@ __device__ __forceinline__ void prefix_x(const Group<P, NW, PPL, F> &G,
 // Phases A1 and A2 in one pass (five prefix fields per slot): the x-moment
 // prefixes W, X, XX in fields 0..2 and the prefix pair of y in fields 3, 4,
 // extended by e (two group scans of 3 and 2 quantities: one scan of all
-// five holds more registers at once).
+// five holds more registers at once).  With the extension written inside
+// the builds, the first build needs no trailing barrier (nothing reads its
+// prefixes before the second build's), and the second exchanges its totals
+// in slots of its own.
 template <class P, int NW, int PPL, int F>
 __device__ __forceinline__ void prefix_xy(const Group<P, NW, PPL, F> &G,
                                           const typename P::S (&x)[PPL],
@@ -655,7 +677,7 @@ __device__ __forceinline__ void prefix_xy(const Group<P, NW, PPL, F> &G,
         }
         S *const Pf[3] = {G.Q, G.Q + 1, G.Q + 2};
         S T[3];
-        build_prefix<P, NW, PPL, 3, kFused>(G, Pf, q, T, e);
+        build_prefix<P, NW, PPL, 3, kFused, F, !kFused>(G, Pf, q, T, e);
         if constexpr (!kFused) extend3<P, NW, PPL>(G, G.Q, G.Q + 1, G.Q + 2, T, e);
     }
     {
@@ -667,7 +689,7 @@ __device__ __forceinline__ void prefix_xy(const Group<P, NW, PPL, F> &G,
         }
         S *const Pf[2] = {G.Q + 3, G.Q + 4};
         S T[2];
-        build_prefix<P, NW, PPL, 2, kFused>(G, Pf, q, T, e);
+        build_prefix<P, NW, PPL, 2, kFused, F, true, 4 * NW>(G, Pf, q, T, e);
         if constexpr (!kFused) extend2<P, NW, PPL>(G, G.Q + 3, G.Q + 4, T, e);
     }
 }
@@ -757,7 +779,11 @@ __device__ double supersmoother(const Group<P, NW, PPL, F> &G, const TrialLaunch
     if constexpr (kDB) {
         // one group vote for the three residual arrays (a fallback leaves an
         // array without marked residuals unchanged)
-        const bool any_neg = group_any_neg3<P, NW, PPL>(G, r0, r1, r2);
+        bool bad = false;
+#pragma unroll
+        for (int p = 0; p < PPL; ++p)
+            bad |= (t * PPL + p < n) && (r0[p] < R(0) || r1[p] < R(0) || r2[p] < R(0));
+        const bool any_neg = __syncthreads_or(bad) != 0;
         cv_fallback<P, NW, PPL>(G, any_neg, r0);
         cv_fallback<P, NW, PPL>(G, any_neg, r1);
         cv_fallback<P, NW, PPL>(G, any_neg, r2);
@@ -814,7 +840,7 @@ __device__ double supersmoother(const Group<P, NW, PPL, F> &G, const TrialLaunch
     }
     // midrange smooth of the chosen spans, clip, blend
     smooth_with<P, NW, PPL, kB2>(G, b1, g1, w, wx, sel, eb, rt);
-    const R ilo = R(1) / (sp0 - sp1), ihi = R(1) / (sp2 - sp1);
+    const R ilo = G.ilo, ihi = G.ihi;
 #pragma unroll
     for (int p = 0; p < PPL; ++p) {
         R sj = rt[p];
@@ -908,7 +934,7 @@ __device__ double single_pass(const Group<P, NW, PPL, F> &G, const TrialLaunch &
             }
             const R sp0 = (R)L.span[0], sp1 = (R)L.span[1], sp2 = (R)L.span[2];
             const R spk[3] = {sp0, sp1, sp2};
-            const R ilo = R(1) / (sp0 - sp1), ihi = R(1) / (sp2 - sp1);
+            const R ilo = G.ilo, ihi = G.ihi;
             const double alpha = L.alpha;
             const bool bass = alpha > 0.0 && alpha <= 10.0;
             const R ex = (R)(10.0 - alpha);
@@ -1032,6 +1058,34 @@ struct ObjData {
 // (48-bit phase, point index in the low 16 bits), G.ties, G.vsmlsq.  Needs
 // only the times, so objects that share them share this step.  Returns true
 // when the sorted phases do not spread (Listing 1's constant fit).
+// Phase key of point j with time x at frequency f: the 48-bit fixed-point
+// phase in the high bits, j in the low 16 (stable order on equal phases);
+// all ones for padding slots (j >= n).
+__device__ __forceinline__ uint64_t phase_key(double x, double f, int j, int n) {
+    // fraction of the exact product tt f (one rounding, the same for every
+    // point); clamped at 0 where tt f lies just below an integer that its
+    // rounded value reached, so that ph is always in [0, 1)
+    const double ph = fmax(fma(x, f, -floor(x * f)), 0.0);
+    // floor(ph 2^48), an integer below 2^48: adding 2^52 places it exactly
+    // in the low mantissa bits (cheaper than a general double -> uint64)
+    const double q = floor(ph * 0x1p48) + 0x1p52;
+    const uint64_t ph48 = __builtin_bit_cast(uint64_t, q) & ((1ull << 52) - 1);
+    return j < n ? ((ph48 << 16) | (uint64_t)j) : ~0ull;
+}
+
+// Flat-phase test and the smallest-variance threshold from the sorted keys
+// (shared by both sorts).
+template <class P, int NW, int PPL, int F>
+__device__ __forceinline__ bool sorted_scale(Group<P, NW, PPL, F> &G, const uint64_t *SK) {
+    const int n = G.n;
+    if ((SK[n - 1] >> 16) <= (SK[0] >> 16)) return true;
+    const int q = n / 4;
+    const double scale =
+        (double)(SK[3 * q - 1] >> 16) * 0x1p-48 - (double)(SK[q - 1] >> 16) * 0x1p-48;
+    G.vsmlsq = listing_vsmlsq(scale);
+    return false;
+}
+
 template <class P, int NW, int PPL, bool CACHE_TT, int F>
 __device__ bool fold_sort(Group<P, NW, PPL, F> &G, unsigned char *lds, const Layout &Y,
                           const double *tt_global, double f) {
@@ -1043,27 +1097,18 @@ __device__ bool fold_sort(Group<P, NW, PPL, F> &G, unsigned char *lds, const Lay
 #pragma unroll
     for (int p = 0; p < PPL; ++p) {
         const int j = t * PPL + p;
-        const double x = (CACHE_TT ? ct : tt_global)[min(j, n - 1)];
-        // fraction of the exact product tt f (one rounding, the same for every
-        // point); clamped at 0 where tt f lies just below an integer that its
-        // rounded value reached, so that ph is always in [0, 1)
-        const double ph = fmax(fma(x, f, -floor(x * f)), 0.0);
-        // floor(ph 2^48), an integer below 2^48: adding 2^52 places it exactly
-        // in the low mantissa bits (cheaper than a general double -> uint64)
-        const double q = floor(ph * 0x1p48) + 0x1p52;
-        const uint64_t ph48 = __builtin_bit_cast(uint64_t, q) & ((1ull << 52) - 1);
-        key[p] = j < n ? ((ph48 << 16) | (uint64_t)j) : ~0ull;
+        key[p] = phase_key((CACHE_TT ? ct : tt_global)[min(j, n - 1)], f, j, n);
     }
     // ---- bucket sort in LDS: NP buckets on the top phase bits, counts by LDS
     // atomics, a group scan for the bucket starts, then the exact rank inside
-    // a bucket by comparing against its (few) members.
-    uint32_t *cnt = (uint32_t *)lds;
-    uint64_t *tmp = (uint64_t *)(lds + ((NP + 1) * 4 + 15) / 16 * 16);
+    // a bucket by comparing against its (few) members.  The counters are
+    // zero on entry (cleared at the end of the previous sort, behind at least
+    // one group barrier); the bucketed keys go to the prefix region, which
+    // is dead until the smoother starts and is first written after two
+    // barriers here.
+    uint32_t *cnt = (uint32_t *)(lds + Y.cnt);
+    uint64_t *tmp = (uint64_t *)lds;
     uint64_t *SK = (uint64_t *)(lds + Y.sk);
-    bsync<NW>();
-#pragma unroll
-    for (int p = 0; p < PPL; ++p) cnt[t * PPL + p] = 0u;
-    bsync<NW>();
     int bkt[PPL];
     uint32_t slot[PPL];
 #pragma unroll
@@ -1103,34 +1148,34 @@ __device__ bool fold_sort(Group<P, NW, PPL, F> &G, unsigned char *lds, const Lay
         if (j < n) tmp[cnt[bkt[p]] + slot[p]] = key[p];
     }
     bsync<NW>();
+    // rank inside the bucket; equal phases share a bucket, so a tie is two
+    // members of one bucket with the same phase
+    bool tie = false;
 #pragma unroll
     for (int p = 0; p < PPL; ++p) {
         const int j = t * PPL + p;
         if (j < n) {
             const uint32_t s = cnt[bkt[p]], e = cnt[bkt[p] + 1];
+            const uint64_t ph = key[p] >> 16;
             uint32_t rank = 0;
-            for (uint32_t i = s; i < e; ++i) rank += tmp[i] < key[p] ? 1u : 0u;
+            for (uint32_t i = s; i < e; ++i) {
+                const uint64_t o = tmp[i];
+                rank += o < key[p] ? 1u : 0u;
+                tie |= (o >> 16) == ph && o != key[p];
+            }
             SK[s + rank] = key[p];
         }
     }
-    bsync<NW>();
-    bool tie = false;
-#pragma unroll
-    for (int p = 0; p < PPL; ++p) {
-        const int j = t * PPL + p;
-        if (j + 1 < n) tie |= (SK[j + 1] >> 16) == (SK[j] >> 16);
-    }
     if constexpr (NW == 1) {
+        wave_lds_sync();
         G.ties = wave_ballot(tie) != 0;
     } else {
         G.ties = __syncthreads_or(tie) != 0;
     }
-    if ((SK[n - 1] >> 16) <= (SK[0] >> 16)) return true;
-    const int q = n / 4;
-    const double scale =
-        (double)(SK[3 * q - 1] >> 16) * 0x1p-48 - (double)(SK[q - 1] >> 16) * 0x1p-48;
-    G.vsmlsq = listing_vsmlsq(scale);
-    return false;
+    // every rank is taken: clear the counters for the next sort
+#pragma unroll
+    for (int p = 0; p < PPL; ++p) cnt[t * PPL + p] = 0u;
+    return sorted_scale(G, SK);
 }
 
 // The smoother and the score of one object on the sorted keys of fold_sort:
@@ -1215,12 +1260,12 @@ __device__ void run_item(Group<P, NW, PPL, F> &G, unsigned char *lds, const Layo
     using R = typename P::R;
     const int64_t ci = item / L.n_tiles;
     const int32_t tile = (int32_t)(item - ci * L.n_tiles);
-    const int obj = L.objs[ci];
+    const int obj = uniform_i32(L.objs[ci]);
     const int64_t part = (int64_t)obj * L.n_tiles + tile;
     int64_t k0, k1;
     if (L.ranges) {
-        k0 = L.ranges[2 * part];
-        k1 = L.ranges[2 * part + 1];
+        k0 = uniform_i64(L.ranges[2 * part]);
+        k1 = uniform_i64(L.ranges[2 * part + 1]);
     } else {
         k0 = (int64_t)tile * L.tile_f;
         k1 = (k0 + L.tile_f < L.n_freq) ? k0 + L.tile_f : L.n_freq;
@@ -1240,12 +1285,12 @@ __device__ void run_item(Group<P, NW, PPL, F> &G, unsigned char *lds, const Layo
         }
         return;
     }
-    const int64_t base = L.cat.offsets[obj];
-    set_length(G, L, (int)(L.cat.offsets[obj + 1] - base));
+    const int64_t base = uniform_i64(L.cat.offsets[obj]);
+    set_length(G, L, (int)(uniform_i64(L.cat.offsets[obj + 1]) - base));
     ObjData<P> od;
-    od.tt = L.cat.tt + base;
-    od.y = (P::kIsF64 ? (const R *)L.cat.yc : (const R *)L.cat.yc32) + base;
-    od.w = (P::kIsF64 ? (const R *)L.cat.w : (const R *)L.cat.w32) + base;
+    od.tt = uniform_ptr(L.cat.tt + base);
+    od.y = uniform_ptr((P::kIsF64 ? (const R *)L.cat.yc : (const R *)L.cat.yc32) + base);
+    od.w = uniform_ptr((P::kIsF64 ? (const R *)L.cat.w : (const R *)L.cat.w32) + base);
     const double chi0 = L.cat.chi0[obj];
     G.inv_chi0 = 1.0 / chi0;
     if constexpr (caches_object(kWave * NW * PPL)) {
@@ -1336,11 +1381,11 @@ __device__ void run_item_shared(Group<P, NW, PPL, F> &G, unsigned char *lds, con
         const double f = grid_freq(L.fmin, L.df, k);
         const bool flat = fold_sort<P, NW, PPL, kCache>(G, lds, Y, L.shared_tt, f);
         for (int m = m0; m < m1; ++m) {
-            const int obj = L.objs[m];
+            const int obj = uniform_i32(L.objs[m]);
             const int64_t row = (int64_t)obj * L.n_freq;
             double Pk = __builtin_nan("");
             if (L.cat.status[obj] == 0) {
-                const int64_t base = L.cat.offsets[obj];
+                const int64_t base = uniform_i64(L.cat.offsets[obj]);
                 const double chi0 = L.cat.chi0[obj];
                 G.inv_chi0 = 1.0 / chi0;
                 const R *yo = (P::kIsF64 ? (const R *)L.cat.yc : (const R *)L.cat.yc32) + base;
@@ -1417,6 +1462,17 @@ void trial_kernel(TrialLaunch L) {
     G.n = 0;
     for (int k = 0; k < 3; ++k) G.hw[k] = 0;
     G.hwf = 0;
+    {  // once per kernel (a select between the two products was otherwise
+       // turned into a division per point)
+        using R = typename P::R;
+        const R sp0 = (R)L.span[0], sp1 = (R)L.span[1], sp2 = (R)L.span[2];
+        G.ilo = R(1) / (sp0 - sp1);
+        G.ihi = R(1) / (sp2 - sp1);
+    }
+    {  // the sort's bucket counters start at zero (and every sort leaves them so)
+        uint32_t *cnt = (uint32_t *)(lds + Y.cnt);
+        for (int i = G.t; i < Y.np; i += kWave * NW) cnt[i] = 0u;
+    }
     // units: the class's objects (or batches of objects sharing their times);
     // queue q hands out the (unit, tile) items of the units with u mod
     // kQueuesPerClass == q, all tiles of a unit in a row.  A workgroup starts

@@ -77,6 +77,31 @@ __device__ __forceinline__ double wave_incl_sum_z(double x, double &z15, double 
     return x;
 }
 
+// M independent scans step by step (the in-row steps of all M first, so
+// that their dependency chains overlap; the two cross-row steps pass the
+// temporaries from one value to the next).
+template <int M>
+__device__ __forceinline__ void wave_incl_sum_z_multi(double (&x)[M], double &z15, double &z31) {
+#pragma unroll
+    for (int m = 0; m < M; ++m) x[m] += dpp_f64<0x111, 0xf, true>(x[m]);
+#pragma unroll
+    for (int m = 0; m < M; ++m) x[m] += dpp_f64<0x112, 0xf, true>(x[m]);
+#pragma unroll
+    for (int m = 0; m < M; ++m) x[m] += dpp_f64<0x114, 0xf, true>(x[m]);
+#pragma unroll
+    for (int m = 0; m < M; ++m) x[m] += dpp_f64<0x118, 0xf, true>(x[m]);
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        z15 = dpp_f64_into<0x142, 0xa>(z15, x[m]);
+        x[m] += z15;
+    }
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        z31 = dpp_f64_into<0x143, 0xc>(z31, x[m]);
+        x[m] += z31;
+    }
+}
+
 __device__ __forceinline__ uint32_t wave_incl_sum_u32(uint32_t v) {
     int x = (int)v;
     x += dpp_i32<0x111, 0xf, true>(x);
