@@ -396,3 +396,64 @@ def test_every_kernel_at_other_spans(ctx, method):
             _assert_pgram_close(pg, po, what=f"kernel {nw}x{ppl} n={n} spans={spans}")
     finally:
         ctx.set_shape(0, 0, 0)
+
+
+def _stress_catalog(seed, n, n_obj=8):
+    """Objects of n points that stress the rare paths: repeated times (each
+    time observed two or three times: exact phase ties at every frequency,
+    whatever the fold's rounding, so tie averaging on both sides), a few
+    points with errors 200x smaller than the rest (leverage w h up to
+    1 - 2e-5: CV residuals divided by a nearly vanishing 1 - w h), clumped
+    times (half the points within 0.02 d), and plain ones."""
+    rng = np.random.default_rng(seed)
+    ts, ys, es = [], [], []
+    for o in range(n_obj):
+        kind = o % 4
+        if kind == 0:
+            t = np.sort(np.repeat(rng.uniform(0, 800, n), rng.integers(2, 4, n))[:n])
+        elif kind == 2:
+            t = np.sort(np.concatenate([rng.uniform(0, 800, n - n // 2),
+                                        rng.uniform(100, 100.02, n // 2)]))
+        else:
+            t = np.sort(rng.uniform(0, 800, n))
+        y = 15 + 0.3 * np.sin(2 * np.pi * t / rng.uniform(0.3, 5.0)) + rng.normal(0, 0.05, n)
+        e = rng.uniform(0.02, 0.08, n)
+        if kind == 1:
+            e[rng.choice(n, max(2, n // 20), replace=False)] *= 0.005
+        ts.append(t)
+        ys.append(y)
+        es.append(e)
+    offs = np.concatenate([[0], np.cumsum([t.size for t in ts])]).astype(np.int64)
+    return offs, np.concatenate(ts), np.concatenate(ys), np.concatenate(es)
+
+
+@pytest.mark.parametrize("method", [oracle.SS, oracle.SSSP, oracle.SSSP2])
+def test_every_kernel_many_items_ties_and_heavy_points(ctx, method):
+    # every compiled FP64 kernel on eight objects that fill most of its group,
+    # one frequency per work item (tile 1) and more items than the persistent
+    # grid has workgroups, so every workgroup takes several items in a row;
+    # a quarter of the objects have exact phase ties at every frequency, a
+    # quarter has points of leverage close to 1.  (Ties from dyadic times at
+    # frequencies whose period is not a binary fraction would not do: the
+    # kernel's phase, the fraction of the exact product tt f, is exact there,
+    # while the oracle's (tt mod p)/p is off by an ulp, so only one side sees
+    # the tie.)
+    try:
+        ctx.set_tile(1)
+        for i, (nw, ppl) in enumerate(ssg.shapes()):
+            n = min(700, max(5, int(0.85 * 64 * nw * ppl)))
+            nf = 400 if n <= 256 else 160
+            grid = (0.25, 0.25 + nf / 16.0, nf)
+            offs, t, y, e = _stress_catalog(3100 + i, n)
+            assert (np.diff(t[offs[0]:offs[1]]) == 0).sum() >= n // 3
+            ctx.set_shape(0, 0, 0)
+            ctx.set_shape(n, nw, ppl)
+            po, so = oracle.periodogram(method, offs, t, y, e, *grid)
+            pg, sg = _gpu_pgram(ctx, method, offs, t, y, e, grid)
+            if (sg == ssg.OBJ_TOO_LONG).all():
+                continue
+            assert np.array_equal(so, sg)
+            _assert_pgram_close(pg, po, what=f"kernel {nw}x{ppl} n={n} method={method}")
+    finally:
+        ctx.set_shape(0, 0, 0)
+        ctx.set_tile(0)
