@@ -41,6 +41,7 @@ extern "C" {
 #define SS_ERR_HIP (-2)         /* a HIP runtime call failed (message has the hipError text) */
 #define SS_ERR_OOM (-3)         /* workspace allocation failed */
 #define SS_ERR_UNSUPPORTED (-4) /* e.g. an object longer than SS_MAX_POINTS */
+#define SS_ERR_INVARIANT (-5)   /* debug mode: an invariant check failed (message has the counts) */
 
 /* ---- per-object status (obj_status[]) */
 #define SS_OBJ_OK 0
@@ -96,7 +97,8 @@ typedef struct {
  * 0 < alpha <= 10; default 9, the paper's choice for catalogs, Sec. 5.1).
  * fixed_span > 0 replaces the variable span by one smooth at that span
  * (Listing 1's fixed-span branch; for the single-pass variant it leaves one
- * candidate span).  flags: reserved, must be 0. */
+ * candidate span).  flags: 0, or the debug bits below (full-grid calls only:
+ * the periodogram calls and ss_best_period; the other calls reject them). */
 typedef struct {
     double span_min;
     double span_mid;
@@ -106,6 +108,19 @@ typedef struct {
     int32_t precision;
     int32_t flags;
 } ss_params;
+
+/* Debug mode.  SS_FLAG_CHECK_INVARIANTS: after the trials, the call re-runs
+ * the trial kernels' fold and sort (Sec. 2.2) and their window sums
+ * (Listing 1's running-line windows) over the same work items and checks
+ * that the sorted phases increase (keys of equal phase in point order) and
+ * that every window of a used span has a positive weight sum W; it then
+ * waits for the device, keeps the counts (ss_ctx_check_counts) and returns
+ * SS_ERR_INVARIANT if anything is wrong.  Results are those of the call
+ * without the flag.  SS_FLAG_CHECK_SELFTEST (with the first) inverts the
+ * order test, so that every trial of two or more points is reported: a test
+ * that the check reports. */
+#define SS_FLAG_CHECK_INVARIANTS 1
+#define SS_FLAG_CHECK_SELFTEST 2
 
 /* A catalog of light curves in CSR form (device memory, FP64):
  * object o owns points offsets[o] .. offsets[o+1]-1 of t (days), y
@@ -451,6 +466,11 @@ const char *ss_last_error(void);
 
 /* ABI version (major*100 + minor). */
 int ss_version(void);
+
+/* Counts of the last call made with SS_FLAG_CHECK_INVARIANTS on this
+ * context: out[0] trials checked, out[1] adjacent sorted keys out of order,
+ * out[2] windows with W <= 0 (all 0 before such a call).  Host memory. */
+int ss_ctx_check_counts(ss_ctx *ctx, int64_t *out);
 
 #ifdef __cplusplus
 }

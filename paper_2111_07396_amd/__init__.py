@@ -19,6 +19,8 @@ LIB_PATH = os.path.join(_HERE, "libssgpu.so")
 
 SS_OK = 0
 SS_ERR_INVALID_ARG, SS_ERR_HIP, SS_ERR_OOM, SS_ERR_UNSUPPORTED = -1, -2, -3, -4
+SS_ERR_INVARIANT = -5
+SS_FLAG_CHECK_INVARIANTS, SS_FLAG_CHECK_SELFTEST = 1, 2
 SS_FP64, SS_FP32C = 0, 1
 SS_METHOD_SS, SS_METHOD_SSSP, SS_METHOD_SSSP_GV = 0, 1, 2
 OBJ_OK, OBJ_TOO_FEW, OBJ_BAD_ERR, OBJ_NONFINITE, OBJ_CONST_MAG = 0, 1, 2, 3, 4
@@ -35,7 +37,8 @@ EXPORTED = ("ss_params_default", "ss_ctx_create", "ss_ctx_destroy", "ss_periodog
             "ss_model_save", "ss_model_load", "ss_model_file_write", "ss_model_file_read",
             "ss_train_step", "ss_best_period_learned", "ss_model_copy_params",
             "ss_shared_periodogram", "ss_shared_best_period", "ss_plan_batches",
-            "ss_periodogram_batched", "ss_best_period_noalloc", "ss_ctx_set_concurrency")
+            "ss_periodogram_batched", "ss_best_period_noalloc", "ss_ctx_set_concurrency",
+            "ss_ctx_check_counts")
 ENC_PARAMS = 145536
 ENC_BINS = 1024
 
@@ -132,6 +135,8 @@ def load_library(path: str = LIB_PATH):
     lib.ss_ctx_trial_kernel_ms.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
                                            ctypes.POINTER(ctypes.c_int32)]
     lib.ss_ctx_trial_kernel_ms.restype = ctypes.c_int
+    lib.ss_ctx_check_counts.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
+    lib.ss_ctx_check_counts.restype = ctypes.c_int
     lib.ss_last_error.argtypes = []
     lib.ss_last_error.restype = ctypes.c_char_p
     lib.ss_version.argtypes = []
@@ -364,6 +369,13 @@ class Context:
         n = ctypes.c_int32(0)
         _check(_lib.ss_ctx_trial_kernel_ms(self._h, ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
+
+    def check_counts(self):
+        """(trials, keys out of order, windows with W <= 0) of the last call made
+        with SS_FLAG_CHECK_INVARIANTS on this context."""
+        out = (ctypes.c_int64 * 3)()
+        _check(_lib.ss_ctx_check_counts(self._h, out))
+        return tuple(int(v) for v in out)
 
     def _pgram(self, fn, cat: DeviceCatalog, grid, params: Params, out=None, status=None,
                stream=None):

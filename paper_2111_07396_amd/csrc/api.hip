@@ -133,6 +133,8 @@ struct ss_ctx {
     hipEvent_t fork_ev = nullptr, join_ev[kNumShapes] = {};
     int64_t chunk_bytes = 0;  // batched periodogram: the current output chunk
     DevBuf chunk;
+    DevBuf dbg;                      // debug mode: device counters of the invariant checks
+    int64_t check_counts[3] = {0, 0, 0};  // their values after the last checked call
 };
 
 // A learned frequency proposal bound to one search grid: the encoder's FP32
@@ -191,7 +193,17 @@ int check_common(ss_ctx *ctx, const ss_catalog *cat, const ss_grid *grid, const 
     if (!std::isfinite(prm->alpha)) return fail(SS_ERR_INVALID_ARG, "alpha must be finite");
     if (prm->precision != SS_FP64 && prm->precision != SS_FP32C)
         return fail(SS_ERR_INVALID_ARG, "precision must be SS_FP64 or SS_FP32C");
-    if (prm->flags != 0) return fail(SS_ERR_INVALID_ARG, "flags must be 0");
+    if ((prm->flags & ~(SS_FLAG_CHECK_INVARIANTS | SS_FLAG_CHECK_SELFTEST)) != 0)
+        return fail(SS_ERR_INVALID_ARG, "unknown flag bits");
+    if ((prm->flags & SS_FLAG_CHECK_SELFTEST) && !(prm->flags & SS_FLAG_CHECK_INVARIANTS))
+        return fail(SS_ERR_INVALID_ARG, "SS_FLAG_CHECK_SELFTEST needs SS_FLAG_CHECK_INVARIANTS");
+    return SS_OK;
+}
+
+// Entry points other than the full-grid searches take no debug flags.
+int no_flags(const ss_params *prm) {
+    if (prm && prm->flags != 0)
+        return fail(SS_ERR_INVALID_ARG, "debug flags are taken by the full-grid calls only");
     return SS_OK;
 }
 
@@ -307,24 +319,10 @@ int ensure_side_streams(ss_ctx *ctx) {
     return SS_OK;
 }
 
-// One persistent trial launch per shape class that can receive objects,
-// over n_tiles items per object (full-grid tiles, or refine ranges), then
-// the finalize step when the best period is wanted.
-int trials(ss_ctx *ctx, const Plan &P, int method, const ss_catalog *cat, const ss_grid *grid,
-           const ss_params *prm, double *pgram64, float *pgram32, bool want_best,
-           int32_t *obj_status, hipStream_t stream, int64_t *best_idx, double *best_period,
-           double *best_power, int32_t tile, int32_t n_tiles, const int64_t *ranges,
-           void *pdm = nullptr, int32_t pdm_bins = 0, int shared_class = -1,
-           int32_t shared_batch = 0, int32_t shared_n = 0, const double *shared_tt = nullptr) {
-    const int64_t n_obj = cat->n_obj;
-    if (want_best && !ctx->fixed) {
-        SS_HIP_TRY(ctx->part_p.ensure((size_t)n_obj * n_tiles * 8), "workspace");
-        SS_HIP_TRY(ctx->part_k.ensure((size_t)n_obj * n_tiles * 4), "workspace");
-        ctx->cur.part_p = (double *)ctx->part_p.p;
-        ctx->cur.part_k = (int32_t *)ctx->part_k.p;
-    }
-    int32_t *counts = ctx->cur.counts;
-    unsigned long long *queues = ctx->cur.queues;
+// The launch description common to the classes of one call (no outputs).
+TrialLaunch base_launch(const ss_ctx *ctx, int method, const ss_catalog *cat,
+                        const ss_grid *grid, const ss_params *prm, int32_t *obj_status,
+                        int32_t tile, int32_t n_tiles) {
     TrialLaunch L{};
     L.cat.offsets = cat->offsets;
     L.cat.tt = ctx->cur.tt;
@@ -345,6 +343,68 @@ int trials(ss_ctx *ctx, const Plan &P, int method, const ss_catalog *cat, const 
     L.alpha = prm->alpha;
     L.fixed_span = prm->fixed_span;
     L.method = method;
+    return L;
+}
+
+// Class c's part of a launch: its object list, count, queues and extension.
+TrialLaunch class_launch(const TrialLaunch &L, const ss_ctx *ctx, const Plan &P, int c,
+                         int64_t n_obj) {
+    TrialLaunch Lc = L;
+    Lc.objs = ctx->cur.objs + (int64_t)c * n_obj;
+    Lc.count = ctx->cur.counts + c;
+    Lc.queue = ctx->cur.queues + (size_t)c * kQueuesPerClass;
+    Lc.ext = P.ext[c];
+    return Lc;
+}
+
+// Debug mode (SS_FLAG_CHECK_INVARIANTS): after the trials, the invariant
+// check kernels over the same items and classes; waits for the device and
+// fails with SS_ERR_INVARIANT when a sorted key or a window weight is wrong.
+int run_checks(ss_ctx *ctx, const Plan &P, int method, const ss_catalog *cat,
+               const ss_grid *grid, const ss_params *prm, int32_t *obj_status,
+               hipStream_t stream, int32_t tile, int32_t n_tiles) {
+    const int64_t n_obj = cat->n_obj;
+    SS_HIP_TRY(ctx->dbg.ensure(4 * sizeof(unsigned long long)), "workspace");
+    unsigned long long *d = (unsigned long long *)ctx->dbg.p;
+    unsigned long long h[4] = {0, 0, 0, 0};
+    SS_HIP_TRY(hipMemcpyAsync(d, h, sizeof(h), hipMemcpyHostToDevice, stream), "debug counters");
+    const TrialLaunch L = base_launch(ctx, method, cat, grid, prm, obj_status, tile, n_tiles);
+    const int selftest = (prm->flags & SS_FLAG_CHECK_SELFTEST) ? 1 : 0;
+    for (int c = 0; c < kNumShapes; ++c) {
+        if (!P.used[c] || !((P.R.runnable >> c) & 1u)) continue;
+        const TrialLaunch Lc = class_launch(L, ctx, P, c, n_obj);
+        SS_HIP_TRY(launch_checks(shape_id(kShapes[c].nw, kShapes[c].ppl), Lc,
+                                 n_obj * (int64_t)n_tiles, ctx->n_cu, d, selftest, stream),
+                   "check kernel");
+    }
+    SS_HIP_TRY(hipMemcpyAsync(h, d, sizeof(h), hipMemcpyDeviceToHost, stream), "debug counters");
+    SS_HIP_TRY(hipStreamSynchronize(stream), "debug counters");
+    for (int i = 0; i < 3; ++i) ctx->check_counts[i] = (int64_t)h[i];
+    if (h[1] != 0 || h[2] != 0)
+        return fail(SS_ERR_INVARIANT, "invariant check: " + std::to_string(h[1]) +
+                                          " sorted keys out of order, " + std::to_string(h[2]) +
+                                          " windows with W <= 0, in " + std::to_string(h[0]) +
+                                          " trials");
+    return SS_OK;
+}
+
+// One persistent trial launch per shape class that can receive objects,
+// over n_tiles items per object (full-grid tiles, or refine ranges), then
+// the finalize step when the best period is wanted.
+int trials(ss_ctx *ctx, const Plan &P, int method, const ss_catalog *cat, const ss_grid *grid,
+           const ss_params *prm, double *pgram64, float *pgram32, bool want_best,
+           int32_t *obj_status, hipStream_t stream, int64_t *best_idx, double *best_period,
+           double *best_power, int32_t tile, int32_t n_tiles, const int64_t *ranges,
+           void *pdm = nullptr, int32_t pdm_bins = 0, int shared_class = -1,
+           int32_t shared_batch = 0, int32_t shared_n = 0, const double *shared_tt = nullptr) {
+    const int64_t n_obj = cat->n_obj;
+    if (want_best && !ctx->fixed) {
+        SS_HIP_TRY(ctx->part_p.ensure((size_t)n_obj * n_tiles * 8), "workspace");
+        SS_HIP_TRY(ctx->part_k.ensure((size_t)n_obj * n_tiles * 4), "workspace");
+        ctx->cur.part_p = (double *)ctx->part_p.p;
+        ctx->cur.part_k = (int32_t *)ctx->part_k.p;
+    }
+    TrialLaunch L = base_launch(ctx, method, cat, grid, prm, obj_status, tile, n_tiles);
     L.pgram64 = pgram64;
     L.pgram32 = pgram32;
     L.part_p = want_best ? ctx->cur.part_p : nullptr;
@@ -355,6 +415,7 @@ int trials(ss_ctx *ctx, const Plan &P, int method, const ss_catalog *cat, const 
     L.pdm_bins = pdm_bins;
     ctx->n_timed = 0;
     int n_launch = 0;
+
     for (int c = 0; c < kNumShapes; ++c)
         if (P.used[c] && ((P.R.runnable >> c) & 1u)) ++n_launch;
     // several classes: fork them onto the side streams so that one class's
@@ -369,11 +430,7 @@ int trials(ss_ctx *ctx, const Plan &P, int method, const ss_catalog *cat, const 
     int launched = 0;
     for (int c = 0; c < kNumShapes; ++c) {
         if (!P.used[c] || !((P.R.runnable >> c) & 1u)) continue;
-        TrialLaunch Lc = L;
-        Lc.objs = ctx->cur.objs + (int64_t)c * n_obj;
-        Lc.count = counts + c;
-        Lc.queue = queues + (size_t)c * kQueuesPerClass;
-        Lc.ext = P.ext[c];
+        TrialLaunch Lc = class_launch(L, ctx, P, c, n_obj);
         if (c == shared_class) {
             Lc.shared_batch = shared_batch;
             Lc.shared_n = shared_n;
@@ -434,8 +491,10 @@ int run(ss_ctx *ctx, int method, const ss_catalog *cat, const ss_grid *grid,
     Plan P;
     int rc = prepare(ctx, method, cat, prm, obj_status, stream, P);
     if (rc != SS_OK) return rc;
-    return trials(ctx, P, method, cat, grid, prm, pgram64, pgram32, want_best, obj_status, stream,
-                  best_idx, best_period, best_power, tile, n_tiles, nullptr, pdm, pdm_bins);
+    rc = trials(ctx, P, method, cat, grid, prm, pgram64, pgram32, want_best, obj_status, stream,
+                best_idx, best_period, best_power, tile, n_tiles, nullptr, pdm, pdm_bins);
+    if (rc != SS_OK || !(prm->flags & SS_FLAG_CHECK_INVARIANTS)) return rc;
+    return run_checks(ctx, P, method, cat, grid, prm, obj_status, stream, tile, n_tiles);
 }
 
 // Objects that share one time sampling: a CSR view (offsets o*n, built on
@@ -489,6 +548,8 @@ int check_shared(ss_ctx *ctx, const ss_shared_catalog *sc, const ss_grid *grid,
     ss_catalog cat{sc->n_obj, sc->n_obj * sc->n_points, (const int64_t *)sc->t, sc->t, sc->y,
                    sc->e};
     int rc = check_common(ctx, &cat, grid, prm);
+    if (rc != SS_OK) return rc;
+    rc = no_flags(prm);
     if (rc != SS_OK) return rc;
     if (sc->n_obj > 0 && sc->n_points > 0 && (!sc->t || !sc->y || !sc->e))
         return fail(SS_ERR_INVALID_ARG, "null catalog pointer");
@@ -895,6 +956,8 @@ int ss_best_period_noalloc(ss_ctx *ctx, int32_t method, const ss_catalog *cat,
                            void *stream) {
     int rc = check_common(ctx, cat, grid, params);
     if (rc != SS_OK) return rc;
+    rc = no_flags(params);
+    if (rc != SS_OK) return rc;
     if (method != SS_METHOD_SS && method != SS_METHOD_SSSP && method != SS_METHOD_SSSP_GV)
         return fail(SS_ERR_INVALID_ARG, "method must be SS_METHOD_SS, _SSSP or _SSSP_GV");
     if (cat->n_obj > 0 && (!best_idx || !best_period || !best_power || !obj_status))
@@ -1079,6 +1142,8 @@ int ss_refine_best_period(ss_ctx *ctx, int32_t method, const ss_catalog *cat,
                           void *stream) {
     int rc = check_common(ctx, cat, grid, params);
     if (rc != SS_OK) return rc;
+    rc = no_flags(params);
+    if (rc != SS_OK) return rc;
     rc = check_learned(cat, top_k, margin, full_below);
     if (rc != SS_OK) return rc;
     if (method != SS_METHOD_SS && method != SS_METHOD_SSSP && method != SS_METHOD_SSSP_GV)
@@ -1100,6 +1165,8 @@ int ss_learned_best_period(ss_ctx *ctx, int32_t method, const ss_catalog *cat,
                            int64_t *best_idx, double *best_period, double *best_power,
                            int32_t *obj_status, void *stream) {
     int rc = check_common(ctx, cat, grid, params);
+    if (rc != SS_OK) return rc;
+    rc = no_flags(params);
     if (rc != SS_OK) return rc;
     rc = check_learned(cat, top_k, margin, full_below);
     if (rc != SS_OK) return rc;
@@ -1449,6 +1516,12 @@ int ss_best_period_learned(ss_ctx *ctx, const ss_model *model, int32_t method,
 
 const char *ss_last_error(void) { return g_last_error.c_str(); }
 
-int ss_version(void) { return 150; }
+int ss_version(void) { return 151; }
+
+int ss_ctx_check_counts(ss_ctx *ctx, int64_t *out) {
+    if (!ctx || !out) return fail(SS_ERR_INVALID_ARG, "null argument");
+    for (int i = 0; i < 3; ++i) out[i] = ctx->check_counts[i];
+    return SS_OK;
+}
 
 }  // extern "C"

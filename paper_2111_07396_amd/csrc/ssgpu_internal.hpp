@@ -131,6 +131,12 @@ hipError_t launch_prep(const int64_t *offsets, const double *t, const double *y,
 hipError_t launch_shared_layout(const double *t, int64_t n, int64_t n_obj, int64_t *offsets,
                                 double *shared_tt, hipStream_t stream);
 
+// Debug mode: the invariant checks of the trial kernels' sort and windows over
+// one class's items; adds to counts[0..2] (trials, unordered sorted keys,
+// windows with W <= 0).
+hipError_t launch_checks(int shape_id, const TrialLaunch &L, int64_t max_items, int n_cu,
+                         unsigned long long *counts, int selftest, hipStream_t s);
+
 // Persistent launch of one class: grid = co-resident workgroups (at most
 // max_items).
 hipError_t launch_trials(int shape_id, int precision, const TrialLaunch &L, int64_t max_items,

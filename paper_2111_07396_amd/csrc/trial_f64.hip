@@ -13,6 +13,11 @@ int trial_lds_bytes(int nw, int ppl, int ext, int method) {
 
 int trial_halfwidth(int n, double span) { return halfwidth(n, span); }
 
+hipError_t launch_checks(int shape, const TrialLaunch &L, int64_t max_items, int n_cu,
+                         unsigned long long *counts, int selftest, hipStream_t s) {
+    return launch_checks_shape(shape, L, max_items, n_cu, counts, selftest, s);
+}
+
 hipError_t launch_trials(int shape, int precision, const TrialLaunch &L, int64_t max_items,
                          int n_cu, hipStream_t s) {
     return precision == 0 ? launch_policy<F64>(shape, L, max_items, n_cu, s)

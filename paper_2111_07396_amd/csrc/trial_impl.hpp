@@ -1545,6 +1545,140 @@ hipError_t launch_cls(const TrialLaunch &L, int64_t max_items, int n_cu, hipStre
     return hipErrorInvalidValue;
 }
 
+// ------------------------------------------------------------------ invariant checks
+// Debug mode: the sort and the window code of the trial kernels run again
+// over the same work items (the FP64 policy, the single-pass layout), and
+// three counters are added to: trials checked, adjacent sorted keys that do
+// not increase (keys carry the point index, so they are unique and must
+// increase strictly: phases ascending, equal phases in index order), and
+// windows of a used span whose weight sum W is not positive.  selftest
+// inverts the order test, so that every trial of two or more points counts
+// (to show that a violation is reported).  Non-persistent: workgroups stride
+// over the class's items.
+template <int NW, int PPL>
+__global__ __launch_bounds__(kWave *NW) void check_kernel(TrialLaunch L,
+                                                        unsigned long long *counts,
+                                                        int selftest) {
+    using P = F64;
+    constexpr int F = prefix_arrays(1, NW, PPL);
+    extern __shared__ __align__(16) unsigned char lds[];
+    const Layout Y(NW, PPL, L.ext, 1);
+    Group<P, NW, PPL, F> G;
+    G.Q = (double *)lds;
+    G.SK = (const uint64_t *)(lds + Y.sk);
+    G.xs = (double *)(lds + Y.xch);
+    G.xd = (double *)(lds + Y.xch);
+    G.t = threadIdx.x;
+    G.wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    G.lane = threadIdx.x % kWave;
+    G.ext = Y.ext;
+    G.ties = false;
+    G.vsmlsq = 0.0;
+    G.inv_chi0 = 0.0;
+    G.ilo = G.ihi = 0.0;
+    G.n = 0;
+    G.inv_n = 0.0;
+    for (int k = 0; k < 3; ++k) G.hw[k] = 0;
+    G.hwf = 0;
+    uint32_t *cnt = (uint32_t *)(lds + Y.cnt);
+    for (int i = G.t; i < Y.np; i += kWave * NW) cnt[i] = 0u;
+    unsigned long long n_trials = 0, n_order = 0, n_weight = 0;
+    const long long items = (long long)(*L.count) * L.n_tiles;
+    for (long long item = blockIdx.x; item < items; item += gridDim.x) {
+        const int64_t ci = item / L.n_tiles;
+        const int32_t tile = (int32_t)(item - ci * L.n_tiles);
+        const int obj = uniform_i32(L.objs[ci]);
+        if (L.cat.status[obj] != 0) continue;
+        const int64_t k0 = (int64_t)tile * L.tile_f;
+        const int64_t k1 = (k0 + L.tile_f < L.n_freq) ? k0 + L.tile_f : L.n_freq;
+        const int64_t base = uniform_i64(L.cat.offsets[obj]);
+        bsync<NW>();
+        set_length(G, L, (int)(uniform_i64(L.cat.offsets[obj + 1]) - base));
+        const int n = G.n;
+        // the object's times and weights: cached in LDS as the trial kernels
+        // do for groups of up to 1,024 points, else read from global memory
+        constexpr bool kCache = caches_object(kWave * NW * PPL);
+        const double *ct = L.cat.tt + base, *cw = L.cat.w + base;
+        if constexpr (kCache) {
+            double *lt = (double *)(lds + Y.obj), *lw = (double *)(lds + Y.obj + 2 * Y.np * 8);
+            for (int i = G.t; i < n; i += kWave * NW) {
+                lt[i] = ct[i];
+                lw[i] = cw[i];
+            }
+            ct = lt;
+            cw = lw;
+        }
+        bsync<NW>();
+        const int fixed = L.fixed_span > 0.0;
+        const int e = fixed ? G.hwf : G.hw[2];
+        for (int64_t k = k0; k < k1; ++k) {
+            const double f = grid_freq(L.fmin, L.df, k);
+            const bool flat = fold_sort<P, NW, PPL, kCache>(G, lds, Y, ct, f);
+            if (G.t == 0) ++n_trials;
+#pragma unroll
+            for (int p = 0; p < PPL; ++p) {
+                const int j = G.t * PPL + p;
+                if (j + 1 < n) {
+                    const bool up = G.SK[j + 1] > G.SK[j];
+                    n_order += (selftest ? up : !up) ? 1u : 0u;
+                }
+            }
+            if (flat) continue;
+            double x[PPL], w[PPL], wx[PPL];
+#pragma unroll
+            for (int p = 0; p < PPL; ++p) {
+                const int j = G.t * PPL + p;
+                const uint64_t key = j < n ? G.SK[j] : 0ull;
+                w[p] = j < n ? cw[(int)(key & 0xffffu)] : 0.0;
+                x[p] = j < n ? P::x_of_key(key) : 0.0;
+                wx[p] = x[p] * w[p];
+            }
+            prefix_x<P, NW, PPL>(G, x, w, wx, e);
+#pragma unroll
+            for (int p = 0; p < PPL; ++p) {
+                const int j = G.t * PPL + p;
+                if (j >= n) continue;
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    if (fixed ? s != 3 : s == 3) continue;
+                    const int b = s == 3 ? G.hwf : G.hw[s];
+                    const double W = G.Q[G.at(j + b + 1)] - G.Q[G.at(j - b)];
+                    n_weight += W > 0.0 ? 0u : 1u;
+                }
+            }
+        }
+    }
+    if (n_trials) atomicAdd(counts, n_trials);
+    if (n_order) atomicAdd(counts + 1, n_order);
+    if (n_weight) atomicAdd(counts + 2, n_weight);
+}
+
+template <int NW, int PPL>
+hipError_t launch_check(const TrialLaunch &L, int64_t max_items, int n_cu,
+                        unsigned long long *counts, int selftest, hipStream_t s) {
+    const Layout Y(NW, PPL, L.ext, 1);
+    const void *fn = (const void *)check_kernel<NW, PPL>;
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, Y.bytes);
+    if (e != hipSuccess) return e;
+    int64_t grid = (int64_t)4 * n_cu;
+    if (grid > max_items) grid = max_items;
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL((check_kernel<NW, PPL>), dim3((unsigned)grid), dim3(kWave * NW),
+                       (size_t)Y.bytes, s, L, counts, selftest);
+    return hipGetLastError();
+}
+
+hipError_t launch_checks_shape(int shape, const TrialLaunch &L, int64_t max_items, int n_cu,
+                               unsigned long long *counts, int selftest, hipStream_t s) {
+    switch (shape) {
+#define SSG_CHECK_CASE(nw, ppl) \
+    case shape_id(nw, ppl): return launch_check<nw, ppl>(L, max_items, n_cu, counts, selftest, s);
+        SSG_SHAPES(SSG_CHECK_CASE)
+#undef SSG_CHECK_CASE
+    }
+    return hipErrorInvalidValue;
+}
+
 template <class P>
 hipError_t launch_policy(int shape, const TrialLaunch &L, int64_t max_items, int n_cu,
                          hipStream_t s) {

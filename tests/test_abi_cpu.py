@@ -31,7 +31,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_version_and_defaults():
     lib = ssg.load_library()
-    assert lib.ss_version() == 150
+    assert lib.ss_version() == 151
     p = ssg._Params()
     lib.ss_params_default(ctypes.byref(p))
     assert (p.span_min, p.span_mid, p.span_max, p.alpha, p.fixed_span, p.precision) == \
