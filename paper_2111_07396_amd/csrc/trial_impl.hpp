@@ -44,7 +44,7 @@ constexpr __host__ __device__ int pad_q(int f, int ppl) {
     return f == 4 ? 2 : ((f * ppl) % 2 == 0 ? 1 : 0);
 }
 template <int F, int PPL>
-__device__ __forceinline__ int qaddr(int u) {
+__host__ __device__ __forceinline__ int qaddr(int u) {
     return u * F + (u / PPL) * pad_q(F, PPL);
 }
 
