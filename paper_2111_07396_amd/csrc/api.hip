@@ -134,6 +134,7 @@ struct ss_ctx {
     int64_t chunk_bytes = 0;  // batched periodogram: the current output chunk
     DevBuf chunk;
     DevBuf dbg;                      // debug mode: device counters of the invariant checks
+    unsigned long long dbg_host[4] = {0, 0, 0, 0};  // their staging copy on the host
     int64_t check_counts[3] = {0, 0, 0};  // their values after the last checked call
 };
 
@@ -366,8 +367,10 @@ int run_checks(ss_ctx *ctx, const Plan &P, int method, const ss_catalog *cat,
     const int64_t n_obj = cat->n_obj;
     SS_HIP_TRY(ctx->dbg.ensure(4 * sizeof(unsigned long long)), "workspace");
     unsigned long long *d = (unsigned long long *)ctx->dbg.p;
-    unsigned long long h[4] = {0, 0, 0, 0};
-    SS_HIP_TRY(hipMemcpyAsync(d, h, sizeof(h), hipMemcpyHostToDevice, stream), "debug counters");
+    unsigned long long *h = ctx->dbg_host;  // lives as long as the context
+    for (int i = 0; i < 4; ++i) h[i] = 0;
+    SS_HIP_TRY(hipMemcpyAsync(d, h, 4 * sizeof(*h), hipMemcpyHostToDevice, stream),
+               "debug counters");
     const TrialLaunch L = base_launch(ctx, method, cat, grid, prm, obj_status, tile, n_tiles);
     const int selftest = (prm->flags & SS_FLAG_CHECK_SELFTEST) ? 1 : 0;
     for (int c = 0; c < kNumShapes; ++c) {
@@ -377,7 +380,8 @@ int run_checks(ss_ctx *ctx, const Plan &P, int method, const ss_catalog *cat,
                                  n_obj * (int64_t)n_tiles, ctx->n_cu, d, selftest, stream),
                    "check kernel");
     }
-    SS_HIP_TRY(hipMemcpyAsync(h, d, sizeof(h), hipMemcpyDeviceToHost, stream), "debug counters");
+    SS_HIP_TRY(hipMemcpyAsync(h, d, 4 * sizeof(*h), hipMemcpyDeviceToHost, stream),
+               "debug counters");
     SS_HIP_TRY(hipStreamSynchronize(stream), "debug counters");
     for (int i = 0; i < 3; ++i) ctx->check_counts[i] = (int64_t)h[i];
     if (h[1] != 0 || h[2] != 0)
