@@ -53,9 +53,10 @@ static void check_shape(const double spans[3], double fixed) {
         CHECK(Y.obj + (caches_object(np) ? 3 * np * 8 : 0) <= Y.cnt, "object cache %dx%d", NW, PPL);
         CHECK(Y.cnt + (np + 1) * 4 <= Y.bytes, "sort counters %dx%d", NW, PPL);
         // the sort's bucketed keys (fold_sort: tmp at the prefix region's
-        // start, np keys) and the three scratch arrays of np values of the
-        // rare paths (tie_average, cv_fallback: 8-byte FP64, 4-byte FP32)
-        CHECK(np * 8 <= Y.qbytes, "bucketed keys %dx%d", NW, PPL);
+        // start, np keys, read by the ranking up to index np + kRankU - 1)
+        // and the three scratch arrays of np values of the rare paths
+        // (tie_average, cv_fallback: 8-byte FP64, 4-byte FP32)
+        CHECK((np + kRankU) * 8 <= Y.qbytes, "bucketed keys %dx%d", NW, PPL);
         CHECK(3 * np * 8 <= Y.qbytes, "scratch %dx%d", NW, PPL);
         // exchange slots (8 NW doubles): group_excl of a build with offset
         // XO and M values up to 4 NW + 2 NW (the phase-A y build), the
