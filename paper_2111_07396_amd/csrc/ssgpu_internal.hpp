@@ -87,7 +87,7 @@ __host__ __device__ __forceinline__ double listing_vsmlsq(double scale) {
 // Trial-group shapes (NW wavefronts, PPL points per thread): a light curve of
 // n points runs on any shape with 64*NW*PPL >= n.
 #define SSG_SHAPES(X) \
-    X(1, 1) X(1, 2) X(2, 1) X(1, 3) X(1, 4) X(2, 2) X(4, 1) X(2, 3) X(4, 2) X(4, 4) X(8, 2) \
+    X(1, 1) X(1, 2) X(2, 1) X(1, 3) X(1, 4) X(2, 2) X(4, 1) X(2, 3) X(4, 2) X(2, 4) X(4, 4) X(8, 2) \
     X(8, 4) X(16, 3) X(16, 4)
 constexpr int shape_id(int nw, int ppl) { return nw * 16 + ppl; }
 struct ShapeInfo {

@@ -1460,6 +1460,7 @@ constexpr int waves_per_simd() {
     if (NW == 2 && PPL == 2) return ss ? (F64 ? 3 : 1) : 3;
     if (NW == 4 && PPL == 1) return F64 ? 4 : (ss ? 3 : 1);
     if (NW == 2 && PPL == 3) return 1;  // FP64 SS held to 2 spilled to scratch and miscomputed
+    if (NW == 2 && PPL == 4) return 1;  // FP64 SS miscomputed in an earlier build
     if (NW == 4 && PPL == 2) return ss ? (F64 ? 2 : 1) : 3;
     if (NW == 4 && PPL == 4) return ss ? 1 : 2;
     return 1;

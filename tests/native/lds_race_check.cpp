@@ -5,8 +5,8 @@
 // barrier orders against it (a read that need not see its intended writer),
 // while each group shape's wavefronts run in whatever order the OS gives
 // them between barriers.  The periodograms are also compared with the CPU
-// oracle.  Shapes include 2x4, which the library does not build (it once
-// gave wrong periodograms on the GPU).
+// oracle.  Shapes include 2x4, which once gave wrong periodograms on the GPU
+// in an earlier build.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -221,7 +221,7 @@ int main(int argc, char **argv) {
     run_shape<1, 4>();
     run_shape<4, 1>();
     run_shape<2, 3>();
-    run_shape<2, 4>();  // not built by the library
+    run_shape<2, 4>();  // miscomputed in an earlier build
     run_shape<4, 2>();
     if (big) {
         run_shape<4, 4>();
