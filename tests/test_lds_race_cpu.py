@@ -1,9 +1,9 @@
 """The trial kernels' own source run on the CPU, one thread per lane
 (tests/native/lds_race_check.cpp with the HIP stand-in of tests/native/emu),
-under ThreadSanitizer: for shapes 1x1 .. 4x2 and 2x4, the three methods (plus a fixed span) in FP64 and the
-compensated-FP32 policy on the 256-point shapes, no LDS
-access of one lane may go unordered against another lane's write to the
-same word, and the periodograms must match the CPU oracle at the GPU parity
+under ThreadSanitizer: for shapes 1x1 .. 4x2 and 2x4, the three methods (plus
+a fixed span) in FP64 and the compensated-FP32 policy on the 256-point
+shapes, no LDS access of one lane may go unordered against another lane's
+write to the same word, and the periodograms must match the CPU oracle at the GPU parity
 bar.  A planted unordered access (no barrier between a write and another
 wavefront's read) must be reported, and the same with a barrier must not."""
 import os
