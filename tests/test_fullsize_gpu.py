@@ -4,7 +4,12 @@ oracle can compute one by one: for sampled objects the oracle's full
 periodogram (best index under the usual tie band, best power within
 1e-4 (1 - P)); for the dense single object the oracle's power at sampled
 frequencies and at the GPU's best frequency, plus the fact that no sampled
-frequency beats the GPU's best."""
+frequency beats the GPU's best, and the oracle's full grid reduced to its best
+index and 64 highest trials (tests/golden/dense_c3_peaks.json, written by
+tests/golden/make_dense_c3.py from the oracle alone: ~80 min of CPU)."""
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -84,3 +89,30 @@ def test_dense_object_full_size(ctx, method):
     d = np.abs(pg[ks] - po[0])
     assert np.all(d <= TOL * (1.0 - po[0]) + 1e-12), float(np.max(d / (1 - po[0])))
     assert np.max(po[0]) <= po[0][np.searchsorted(ks, kb)] + TOL * (1 - po[0].max())
+
+
+@pytest.mark.parametrize("method", [oracle.SS, oracle.SSSP])
+def test_dense_object_full_grid_against_oracle_peaks(ctx, method):
+    import torch
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                        "dense_c3_peaks.json")
+    with open(path) as f:
+        gold = json.load(f)
+    rec = gold["methods"]["ss" if method == oracle.SS else "sssp"]
+    cat, grid = synth.single_dense()
+    assert list(grid) == gold["grid"] and rec["status"] == 0
+    dc = ssg.DeviceCatalog.from_numpy(cat.offsets, cat.t, cat.y, cat.e)
+    fn = ctx.ss_periodogram if method == oracle.SS else ctx.sssp_periodogram
+    pg, st = fn(dc, grid)
+    torch.cuda.synchronize()
+    pg = pg.cpu().numpy()[0]
+    top = np.asarray(rec["top"])
+    ks, po = top[:, 0].astype(np.int64), top[:, 1]
+    d = np.abs(pg[ks] - po)
+    assert np.all(d <= TOL * (1.0 - po) + 1e-12), float(np.max(d / (1.0 - po)))
+    # the GPU's best trial is the oracle's, or one of its trials within the tie band
+    kg, pb = int(np.argmax(pg)), rec["p_best"]
+    assert pg[kg] <= pb + TOL * (1.0 - pb) + 1e-12
+    if kg != rec["best"]:
+        near = {int(k): p for k, p in rec["top"]}
+        assert kg in near and pb - near[kg] <= TOL * (1.0 - pb), (kg, rec["best"])
