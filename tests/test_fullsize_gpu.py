@@ -1,8 +1,10 @@
 """Parity at the benchmark's full sizes, in the launch configuration the
 benchmark times (ss_best_period over whole catalogs), checked on outputs the
-oracle can compute one by one: for sampled objects the oracle's full
+oracle can compute one by one: for sampled objects of the N=200 catalog (100
+per method) and of the uneven catalog (40: its shortest and longest curve and
+38 others, FP64 for both methods and FP32c for SS) the oracle's full
 periodogram (best index under the usual tie band, best power within
-1e-4 (1 - P)); for the dense single object the oracle's power at sampled
+1e-4 (1 - P), 1e-3 in FP32c); for the dense single object the oracle's power at sampled
 frequencies and at the GPU's best frequency, plus the fact that no sampled
 frequency beats the GPU's best, and the oracle's full grid reduced to its best
 index and 64 highest trials (tests/golden/dense_c3_peaks.json, written by
@@ -56,6 +58,27 @@ def test_n200_catalog_full_size(ctx, method):
     _check_objects(cat, grid, bi, bw, method, objs)
 
 
+def _uneven_sample(cat, n, seed):
+    """The shortest and the longest curve and n - 2 others of the uneven catalog."""
+    lens = np.diff(cat.offsets)
+    ends = [int(np.argmin(lens)), int(np.argmax(lens))]
+    rest = np.setdiff1d(np.arange(cat.n_obj), ends)
+    return np.sort(np.concatenate([ends, np.random.default_rng(seed).choice(rest, n - 2,
+                                                                            replace=False)]))
+
+
+@pytest.mark.parametrize("method", [oracle.SS, oracle.SSSP])
+def test_uneven_catalog_full_size_fp64(ctx, method):
+    import torch
+    cat, grid = synth.catalog_uneven()
+    dc = ssg.DeviceCatalog.from_numpy(cat.offsets, cat.t, cat.y, cat.e)
+    bi, bp, bw, st = ctx.ss_best_period(method, dc, grid)
+    torch.cuda.synchronize()
+    bi, bw, st = bi.cpu().numpy(), bw.cpu().numpy(), st.cpu().numpy()
+    assert (st == 0).all() and (bi >= 0).all()
+    _check_objects(cat, grid, bi, bw, method, _uneven_sample(cat, 40, 20 + method))
+
+
 def test_uneven_catalog_full_size_fp32c(ctx):
     import torch
     cat, grid = synth.catalog_uneven()
@@ -65,11 +88,8 @@ def test_uneven_catalog_full_size_fp32c(ctx):
     torch.cuda.synchronize()
     bi, bw, st = bi.cpu().numpy(), bw.cpu().numpy(), st.cpu().numpy()
     assert (st == 0).all()
-    lens = np.diff(cat.offsets)
-    objs = [int(np.argmin(lens)), int(np.argmax(lens))] + \
-        list(np.random.default_rng(7).choice(cat.n_obj, 2, replace=False))
     # the FP32c band of the FP32c parity tests
-    _check_objects(cat, grid, bi, bw, oracle.SS, objs, band=1e-3)
+    _check_objects(cat, grid, bi, bw, oracle.SS, _uneven_sample(cat, 40, 7), band=1e-3)
 
 
 @pytest.mark.parametrize("method", [oracle.SS, oracle.SSSP])
